@@ -1,0 +1,168 @@
+"""CPU oracle for MAP accepting-cycle detection -- test infrastructure only.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+use this package.  The product path (the HIP library and its binding) never
+imports, links or calls it, and the two share no code.
+
+The arithmetic lives in ``map_oracle.c`` (plain C, compiled with gcc by
+``build()``); this module marshals numpy arrays.  See the C file's header for
+the method as the paper states it (Section 2) and the readings taken where it
+is silent.
+
+Functions
+---------
+fixpoint(g, acc, mode)  map vector of one fixpoint; mode 'jacobi' (the value
+                        propagation as stated), 'reach' (definition, tiny
+                        graphs) or 'desc' (definition by decreasing accepting
+                        id, O(n+m))
+map_detect(g, ...)      the MAP outer loop: found, witness, K, trace, maps
+digest(map)             order-independent 64-bit digest of a map vector
+jacobi_steps(g, acc)    the vector after every jacobi pass
+tarjan(g)               accepting-cycle verdict from strongly connected components
+ndfs(g)                 accepting-cycle verdict from nested depth-first search
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "map_oracle.c")
+MODES = {"jacobi": 0, "reach": 1, "desc": 2}
+
+
+def build(force: bool = True) -> str:
+    """Compile ``liboracle.so`` next to this file with gcc (single-threaded C)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+        lib.oracle_fixpoint.argtypes = [i32, i64, _i32p, _i32p, _u8p, i32, _i32p, ctypes.POINTER(i64)]
+        lib.oracle_fixpoint.restype = ctypes.c_int
+        lib.oracle_digest.argtypes = [i32, _i32p]
+        lib.oracle_digest.restype = ctypes.c_uint64
+        lib.oracle_map_detect.argtypes = [i32, i64, _i32p, _i32p, _u8p, i32, i32, _i32p, ctypes.POINTER(i64),
+                                          vp, i32, vp, i32, vp]
+        lib.oracle_map_detect.restype = ctypes.c_int
+        lib.oracle_tarjan.argtypes = [i32, i64, _i32p, _i32p, _u8p, vp]
+        lib.oracle_tarjan.restype = ctypes.c_int
+        lib.oracle_ndfs.argtypes = [i32, i64, _i32p, _i32p, _u8p]
+        lib.oracle_ndfs.restype = ctypes.c_int
+        lib.oracle_jacobi_steps.argtypes = [i32, i64, _i32p, _i32p, _u8p, vp, i64]
+        lib.oracle_jacobi_steps.restype = i64
+        _lib = lib
+    return _lib
+
+
+def _arrays(g, acc=None):
+    src = np.ascontiguousarray(g.src, dtype=np.int32)
+    dst = np.ascontiguousarray(g.dst, dtype=np.int32)
+    a = np.ascontiguousarray(g.acc if acc is None else acc, dtype=np.uint8)
+    if a.shape != (g.n,):
+        raise ValueError("accepting vector must have n entries")
+    return src, dst, a
+
+
+def fixpoint(g, acc=None, mode: str = "jacobi"):
+    """Return (map vector int32[n], sweeps) for accepting set ``acc`` (default g.acc)."""
+    src, dst, a = _arrays(g, acc)
+    out = np.zeros(g.n, np.int32)
+    sweeps = ctypes.c_int64(0)
+    rc = _load().oracle_fixpoint(g.n, len(src), src, dst, a, MODES[mode], out, ctypes.byref(sweeps))
+    if rc != 0:
+        raise ValueError(f"oracle_fixpoint failed rc={rc}")
+    return out, int(sweeps.value)
+
+
+def jacobi_steps(g, acc=None, cap: int = 1 << 16) -> np.ndarray:
+    """The vectors after each jacobi pass (the last pass changes nothing)."""
+    src, dst, a = _arrays(g, acc)
+    buf = np.zeros((cap, g.n), np.int32)
+    t = int(_load().oracle_jacobi_steps(g.n, len(src), src, dst, a, buf.ctypes.data, cap))
+    if t < 0:
+        raise ValueError(f"oracle_jacobi_steps failed rc={t}")
+    return buf[:min(t, cap)].copy()
+
+
+def digest(map_vec) -> int:
+    m = np.ascontiguousarray(map_vec, dtype=np.int32)
+    return int(_load().oracle_digest(len(m), m))
+
+
+@dataclass
+class Detect:
+    found: int
+    witness: int
+    iterations: int
+    accepting_left: int
+    sweeps: int
+    status: int
+    trace: np.ndarray      # uint64 [K_recorded, 3]: |Del_k|, sweeps_k, digest_k
+    maps: np.ndarray       # int32 [min(K, maps_cap), n]
+    acc_out: np.ndarray    # uint8 [n]
+
+    @property
+    def verdict(self):
+        return (self.found, self.witness, self.iterations)
+
+
+def map_detect(g, acc=None, mode: str = "desc", max_iterations: int = 0, trace_cap: int | None = None,
+               maps_cap: int = 0) -> Detect:
+    """Run the MAP outer loop on the oracle."""
+    src, dst, a = _arrays(g, acc)
+    n = g.n
+    if trace_cap is None:
+        trace_cap = int(a.sum()) + 1
+    trace = np.zeros((max(trace_cap, 1), 3), np.uint64)
+    maps = np.zeros((max(maps_cap, 0), n), np.int32)
+    acc_out = np.zeros(n, np.uint8)
+    res = np.zeros(4, np.int32)
+    sweeps = ctypes.c_int64(0)
+    rc = _load().oracle_map_detect(n, len(src), src, dst, a, MODES[mode], max_iterations, res,
+                                   ctypes.byref(sweeps), trace.ctypes.data, trace_cap,
+                                   maps.ctypes.data if maps_cap > 0 else None, maps_cap,
+                                   acc_out.ctypes.data)
+    if rc not in (0, -5):
+        raise ValueError(f"oracle_map_detect failed rc={rc}")
+    k = int(res[2])
+    return Detect(found=int(res[0]), witness=int(res[1]), iterations=k, accepting_left=int(res[3]),
+                  sweeps=int(sweeps.value), status=rc, trace=trace[:min(k, trace_cap)].copy(),
+                  maps=maps[:min(k, maps_cap)].copy(), acc_out=acc_out)
+
+
+def tarjan(g, acc=None, with_components: bool = False):
+    src, dst, a = _arrays(g, acc)
+    comp = np.zeros(g.n, np.int32)
+    rc = _load().oracle_tarjan(g.n, len(src), src, dst, a, comp.ctypes.data)
+    if rc < 0:
+        raise ValueError(f"oracle_tarjan failed rc={rc}")
+    return (rc, comp) if with_components else rc
+
+
+def ndfs(g, acc=None) -> int:
+    src, dst, a = _arrays(g, acc)
+    rc = _load().oracle_ndfs(g.n, len(src), src, dst, a)
+    if rc < 0:
+        raise ValueError(f"oracle_ndfs failed rc={rc}")
+    return rc

@@ -1,0 +1,61 @@
+"""Write the stored expected values for the full-size parity cases.
+
+Calls only the CPU oracle and the seeded generators; nothing here touches the
+HIP library.  Run from the repository root:
+
+    python tests/golden/make_goldens.py [config2|config3|all]
+
+Each record holds the verdict (found, witness, K), the accepting count at
+exit, the per-iteration |Del_k| list and the per-iteration map digests
+(SHA-256 over their little-endian uint64 values, plus the first and last
+few values in hex).
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+OUT = os.path.join(ROOT, "tests", "golden", "full_size.json")
+
+
+def record(g, label):
+    t = time.time()
+    d = oracle.map_detect(g, mode="desc")
+    dt = time.time() - t
+    digests = d.trace[:, 2].astype(np.uint64)
+    return {
+        "label": label, "graph": g.name, "n": g.n, "m": g.m, "accepting": g.n_acc,
+        "found": d.found, "witness": d.witness, "iterations": d.iterations,
+        "accepting_left": d.accepting_left,
+        "dels": [int(x) for x in d.trace[:, 0]],
+        "digest_sha256": hashlib.sha256(digests.astype("<u8").tobytes()).hexdigest(),
+        "digest_head": [f"{int(x):016x}" for x in digests[:8]],
+        "digest_tail": [f"{int(x):016x}" for x in digests[-8:]],
+        "oracle_seconds": round(dt, 1),
+    }
+
+
+def main(which):
+    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    if which in ("config2", "all"):
+        data["c2B"] = record(synth.config2(), "config 2 variant B (no accepting cycle)")
+        data["c2A"] = record(synth.config2(planted=True), "config 2 variant A (planted accepting 64-cycle)")
+    if which in ("config3", "all"):
+        data["c3"] = record(synth.config3(), "config 3 (2^25-vertex DAG, 0.1% accepting)")
+    with open(OUT, "w") as f:
+        json.dump(data, f, indent=1)
+    for k, v in data.items():
+        print(k, v["found"], v["witness"], v["iterations"], v["accepting_left"], v["oracle_seconds"])
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else "all")
