@@ -1,0 +1,146 @@
+/*
+ * mapcheck.h -- C ABI of the MI355X (gfx950) MAP accepting-cycle detector.
+ *
+ * Method (Barnat, Brim, Ceska: "DiVinE-CUDA -- A Tool for GPU Accelerated LTL
+ * Model Checking", PDMC 2009, Section 2 "DiVinE CUDA Algorithmics"): detect
+ * whether a directed graph with accepting vertices has a cycle through an
+ * accepting vertex.  Accepting vertices are ordered; for every vertex the
+ * maximal accepting predecessor map(v) is computed by propagating values to
+ * a fixpoint, posed as a repeated sparse matrix-vector product.  An accepting
+ * vertex that is its own maximal accepting predecessor lies on an accepting
+ * cycle; otherwise every accepting vertex that is some vertex's map value loses
+ * its accepting flag and the computation restarts, until a cycle is found or no
+ * accepting vertex is left.  The paper runs MAP on the transposed graph, so on
+ * the generated graph G that callers pass here:
+ *
+ *   map(v) = max { a accepting : v reaches a along >= 1 edge of G },  0 if none.
+ *
+ * Conventions shared by every entry point
+ *   - Vertex ids are int32 1..n; 0 means "none".  Edge lists, map vectors and
+ *     the witness use ids; CSR column arrays hold 0-based vertex indices.
+ *   - The order on accepting vertices is numeric id (larger wins).
+ *   - Accepting flags are uint8[n]; entry i (nonzero = accepting) is id i+1.
+ *   - 1 <= n <= 2^31 - 2 and 0 <= m <= 2^31 - 1, else MAP_ERANGE.
+ *   - Pointers marked "device" must be device memory (hipMalloc or a torch
+ *     CUDA tensor) of the stated length, owned by the caller.  The library
+ *     never allocates or frees device memory; scratch comes from the caller's
+ *     workspace `ws` of at least map_workspace_bytes(n, m, flags) bytes,
+ *     256-byte aligned.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Every
+ *     call only enqueues work on it and returns; nothing synchronizes.  Device
+ *     outputs are valid once the stream has been synchronized.
+ *   - Host-detectable errors (null pointers, sizes, workspace too small) are
+ *     returned before anything is enqueued.  Errors found on the device are
+ *     written to the device status word and the call itself returns MAP_OK.
+ *     A failure of the HIP runtime to launch returns MAP_EDEVICE.
+ *   - Calls on different streams with disjoint outputs and workspaces may
+ *     run concurrently; the library holds no mutable state besides a per-
+ *     device cache of launch limits.
+ */
+#ifndef MAPCHECK_H
+#define MAPCHECK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define MAP_OK 0
+#define MAP_EINVAL (-1)        /* null pointer or unknown flag bits */
+#define MAP_ERANGE (-2)        /* n or m outside the supported range */
+#define MAP_ENOSPC (-3)        /* workspace smaller than map_workspace_bytes */
+#define MAP_EDEVICE (-4)       /* the HIP runtime refused a launch */
+#define MAP_ENOTCONVERGED (-5) /* device: iteration or sweep cap reached */
+#define MAP_ERANGE_DEV (-6)    /* device: an edge endpoint outside 1..n */
+
+/* Flags (bitwise or; 0 = automatic choice). */
+#define MAP_FLAG_DENSE_ONLY 0x1u /* never switch to the sparse (frontier) sweep */
+#define MAP_FLAG_NO_TRACE_DIGEST 0x2u /* leave the digest column of the trace 0 */
+
+/* Result of map_propagate / map_detect, written to device memory (32 bytes). */
+typedef struct map_result {
+  int32_t found;          /* 1 if an accepting cycle was detected, else 0 */
+  int32_t witness;        /* largest id v with map(v) == v in the last iteration, else 0 */
+  int32_t iterations;     /* K: number of fixpoint computations made */
+  int32_t status;         /* MAP_OK, MAP_ENOTCONVERGED */
+  int64_t sweeps;         /* propagation sweeps over all iterations (schedule dependent) */
+  int32_t accepting_left; /* number of accepting vertices at exit */
+  int32_t reserved;
+} map_result;
+
+/*
+ * Bytes of device workspace that map_build_csr, map_propagate and map_detect
+ * need for a graph with n vertices and m edges (host only, no side effects).
+ * Returns 0 when n or m is out of range.
+ */
+size_t map_workspace_bytes(int32_t n, int64_t m, uint32_t flags);
+
+/*
+ * CSR of the graph from its edge list (the paper's adjacency matrix in
+ * compressed sparse row form, built by the tool before propagation; Section 2).
+ *   src, dst   device int32[m]: edge src[i] -> dst[i] of G, ids 1..n.
+ *   row_ptr    device int32[n+1] out: row v (0-based) of the pull CSR lists the
+ *              successors of vertex v+1 in col[row_ptr[v] .. row_ptr[v+1]).
+ *   col        device int32[m] out: 0-based successor indices.
+ *   rrow_ptr,  device int32[n+1] / int32[m] out, or both NULL: the transposed
+ *   rcol       CSR (row v lists the predecessors of vertex v+1), used by the
+ *              sparse sweep.
+ *   status     device int32 out: MAP_OK, or MAP_ERANGE_DEV if an id lies
+ *              outside 1..n (the CSR contents are then unspecified).
+ * Duplicate edges and self-loops are kept.  Column order within a row is
+ * unspecified (it does not affect any result).
+ */
+int map_build_csr(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t *row_ptr,
+                  int32_t *col, int32_t *rrow_ptr, int32_t *rcol, int32_t *status, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/*
+ * One fixpoint of the value propagation (Section 2: every vertex keeps the
+ * largest accepting value that reached it through a successor; repeat until no
+ * value improves), for a given accepting set.
+ *   row_ptr, col    device pull CSR from map_build_csr.
+ *   rrow_ptr, rcol  device transposed CSR, or NULL (dense sweeps only).
+ *   accepting       device uint8[n], not modified.
+ *   map_out         device int32[n] out: map(v) for id v at index v-1.
+ *   result          device map_result out: sweeps and status (found, witness
+ *                   and iterations are 0).
+ */
+int map_propagate(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *rrow_ptr,
+                  const int32_t *rcol, const uint8_t *accepting, int32_t *map_out, map_result *result,
+                  uint32_t flags, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * The MAP outer loop (Section 2), entirely on the device: for k = 1, 2, ...
+ * compute map_k for the accepting set A_k; if some v has map_k(v) == v report a
+ * cycle (witness = the largest such v); otherwise remove the accepting flag of
+ * every nonzero map_k value and continue.  The loop stops when a cycle is
+ * found, when no accepting vertex is left, or when no flag was removed (every
+ * map value is 0, so no accepting cycle exists).
+ *   accepting0     device uint8[n]: A_1, not modified.
+ *   result         device map_result out.
+ *   trace          device uint64[trace_cap][3] out, or NULL: row k-1 holds
+ *                  { |Del_k| (flags removed after iteration k; 0 when it found a
+ *                  cycle or removed none), sweeps of iteration k, digest of
+ *                  map_k = sum over v of mix64((v << 32) | map_k(v)) mod 2^64,
+ *                  mix64 the SplitMix64 finalizer }.  Rows beyond trace_cap are
+ *                  dropped.
+ *   accepting_out  device uint8[n] out, or NULL: the accepting set at exit.
+ *   max_iterations >= 1 caps K (status MAP_ENOTCONVERGED when reached);
+ *                  <= 0 means no cap (K <= |A_1| always holds).
+ */
+int map_detect(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *rrow_ptr,
+               const int32_t *rcol, const uint8_t *accepting0, map_result *result, uint64_t *trace,
+               int32_t trace_cap, uint8_t *accepting_out, int32_t max_iterations, uint32_t flags, void *ws,
+               size_t ws_bytes, void *stream);
+
+/* Static description of a status code. */
+const char *map_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAPCHECK_H */

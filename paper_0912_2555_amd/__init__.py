@@ -1,0 +1,222 @@
+"""MI355X-native MAP accepting-cycle detection (Barnat, Brim, Ceska, PDMC 2009).
+
+Thin Python binding over the C ABI of ``libmapcheck.so`` (declared in
+``include/mapcheck.h``).  Every step of the method runs in the library's HIP
+kernels; this module only marshals arguments.  PyTorch supplies device memory
+(CUDA tensors on ROCm) and the current stream.
+
+The raw calls mirror the C names and never synchronize:
+
+``map_workspace_bytes(n, m, flags)``
+``map_build_csr(n, src, dst, row_ptr, col, rrow_ptr, rcol, status, ws)``
+``map_propagate(n, row_ptr, col, rrow_ptr, rcol, accepting, map_out, result, flags, ws)``
+``map_detect(n, row_ptr, col, rrow_ptr, rcol, accepting0, result, trace, accepting_out, max_iterations, flags, ws)``
+
+Convenience wrappers (``Csr``, ``build_csr``, ``propagate``, ``detect``)
+allocate the tensors, call the raw entry points and synchronize when results
+are read back.
+
+The library must be built (``python -m paper_0912_2555_amd.build``); importing
+this package raises if ``libmapcheck.so`` is missing -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmapcheck.so")
+
+MAP_OK = 0
+MAP_EINVAL = -1
+MAP_ERANGE = -2
+MAP_ENOSPC = -3
+MAP_EDEVICE = -4
+MAP_ENOTCONVERGED = -5
+MAP_ERANGE_DEV = -6
+MAP_FLAG_DENSE_ONLY = 0x1
+MAP_FLAG_NO_TRACE_DIGEST = 0x2
+
+EXPORTS = ("map_workspace_bytes", "map_build_csr", "map_propagate", "map_detect", "map_strerror")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_0912_2555_amd.build` "
+                      "(there is no fallback implementation)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp, _i32, _i64, _u32, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
+_lib.map_workspace_bytes.argtypes = [_i32, _i64, _u32]
+_lib.map_workspace_bytes.restype = _sz
+_lib.map_build_csr.argtypes = [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.map_build_csr.restype = ctypes.c_int
+_lib.map_propagate.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u32, _vp, _sz, _vp]
+_lib.map_propagate.restype = ctypes.c_int
+_lib.map_detect.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _i32, _u32, _vp, _sz, _vp]
+_lib.map_detect.restype = ctypes.c_int
+_lib.map_strerror.argtypes = [ctypes.c_int]
+_lib.map_strerror.restype = ctypes.c_char_p
+
+
+class MapError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {strerror(status)} ({status})")
+        self.status = status
+
+
+def strerror(status: int) -> str:
+    return _lib.map_strerror(int(status)).decode()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch.Tensor or None")
+    if not t.is_cuda:
+        raise ValueError("device tensor required (torch CUDA/HIP tensor)")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor required")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(rc: int, where: str):
+    if rc != MAP_OK:
+        raise MapError(rc, where)
+
+
+# ------------------------------------------------------------ raw C-ABI calls
+
+def map_workspace_bytes(n: int, m: int, flags: int = 0) -> int:
+    return int(_lib.map_workspace_bytes(n, m, flags))
+
+
+def map_build_csr(n, src, dst, row_ptr, col, rrow_ptr, rcol, status, ws, stream=None) -> int:
+    m = 0 if src is None else int(src.numel())
+    return _lib.map_build_csr(n, m, _ptr(src), _ptr(dst), _ptr(row_ptr), _ptr(col), _ptr(rrow_ptr), _ptr(rcol),
+                              _ptr(status), _ptr(ws), 0 if ws is None else ws.numel() * ws.element_size(),
+                              _stream(stream))
+
+
+def map_propagate(n, row_ptr, col, rrow_ptr, rcol, accepting, map_out, result, flags, ws, stream=None) -> int:
+    return _lib.map_propagate(n, _ptr(row_ptr), _ptr(col), _ptr(rrow_ptr), _ptr(rcol), _ptr(accepting),
+                              _ptr(map_out), _ptr(result), flags, _ptr(ws),
+                              0 if ws is None else ws.numel() * ws.element_size(), _stream(stream))
+
+
+def map_detect(n, row_ptr, col, rrow_ptr, rcol, accepting0, result, trace, accepting_out, max_iterations, flags,
+               ws, stream=None) -> int:
+    cap = 0 if trace is None else int(trace.shape[0])
+    return _lib.map_detect(n, _ptr(row_ptr), _ptr(col), _ptr(rrow_ptr), _ptr(rcol), _ptr(accepting0),
+                           _ptr(result), _ptr(trace), cap, _ptr(accepting_out), max_iterations, flags, _ptr(ws),
+                           0 if ws is None else ws.numel() * ws.element_size(), _stream(stream))
+
+
+# ---------------------------------------------------------------- wrappers
+
+@dataclass
+class Result:
+    found: int
+    witness: int
+    iterations: int
+    status: int
+    sweeps: int
+    accepting_left: int
+
+    @property
+    def verdict(self):
+        return (self.found, self.witness, self.iterations)
+
+    @staticmethod
+    def from_tensor(t: torch.Tensor) -> "Result":
+        a = t.detach().cpu().numpy().view(np.int32)
+        sweeps = int(a[4:6].view(np.int64)[0])
+        return Result(int(a[0]), int(a[1]), int(a[2]), int(a[3]), sweeps, int(a[6]))
+
+
+def new_result(device=None) -> torch.Tensor:
+    """A zeroed device map_result (32 bytes, viewed as int32[8])."""
+    return torch.zeros(8, dtype=torch.int32, device=device or "cuda")
+
+
+def workspace(n: int, m: int, flags: int = 0, device=None) -> torch.Tensor:
+    nbytes = map_workspace_bytes(n, m, flags)
+    if nbytes == 0:
+        raise MapError(MAP_ERANGE, "map_workspace_bytes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
+
+
+@dataclass
+class Csr:
+    """Pull CSR of G (row v = successors) and, optionally, the transposed CSR."""
+    n: int
+    m: int
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    rrow_ptr: torch.Tensor | None
+    rcol: torch.Tensor | None
+    status: torch.Tensor
+
+
+def build_csr(n: int, src, dst, transposed: bool = True, ws: torch.Tensor | None = None, stream=None,
+              device="cuda") -> Csr:
+    """Upload (if needed) the 1-based edge list and build the CSR on the device."""
+    src = torch.as_tensor(src, dtype=torch.int32).to(device).contiguous()
+    dst = torch.as_tensor(dst, dtype=torch.int32).to(device).contiguous()
+    m = int(src.numel())
+    row_ptr = torch.empty(n + 1, dtype=torch.int32, device=device)
+    col = torch.empty(max(m, 1), dtype=torch.int32, device=device)
+    rrow_ptr = torch.empty(n + 1, dtype=torch.int32, device=device) if transposed else None
+    rcol = torch.empty(max(m, 1), dtype=torch.int32, device=device) if transposed else None
+    status = torch.zeros(1, dtype=torch.int32, device=device)
+    if ws is None:
+        ws = workspace(n, m, device=device)
+    _check(map_build_csr(n, src if m else None, dst if m else None, row_ptr, col, rrow_ptr, rcol, status, ws,
+                         stream), "map_build_csr")
+    return Csr(n, m, row_ptr, col, rrow_ptr, rcol, status)
+
+
+def propagate(csr: Csr, accepting, flags: int = 0, ws=None, stream=None):
+    """One fixpoint: returns (map vector as a device int32 tensor, Result)."""
+    acc = torch.as_tensor(accepting, dtype=torch.uint8).to(csr.row_ptr.device).contiguous()
+    out = torch.empty(csr.n, dtype=torch.int32, device=csr.row_ptr.device)
+    res = new_result(csr.row_ptr.device)
+    if ws is None:
+        ws = workspace(csr.n, csr.m, flags, device=csr.row_ptr.device)
+    _check(map_propagate(csr.n, csr.row_ptr, csr.col, csr.rrow_ptr, csr.rcol, acc, out, res, flags, ws, stream),
+           "map_propagate")
+    return out, Result.from_tensor(res)
+
+
+@dataclass
+class DetectOut:
+    result: Result
+    trace: np.ndarray | None
+    accepting_out: np.ndarray | None
+
+
+def detect(csr: Csr, accepting0, trace_cap: int = 0, want_acc: bool = False, max_iterations: int = 0,
+           flags: int = 0, ws=None, stream=None) -> DetectOut:
+    """The MAP outer loop on the device; synchronizes to read the result."""
+    dev = csr.row_ptr.device
+    acc = torch.as_tensor(accepting0, dtype=torch.uint8).to(dev).contiguous()
+    res = new_result(dev)
+    trace = torch.zeros((trace_cap, 3), dtype=torch.int64, device=dev) if trace_cap > 0 else None
+    acc_out = torch.zeros(csr.n, dtype=torch.uint8, device=dev) if want_acc else None
+    if ws is None:
+        ws = workspace(csr.n, csr.m, flags, device=dev)
+    _check(map_detect(csr.n, csr.row_ptr, csr.col, csr.rrow_ptr, csr.rcol, acc, res, trace, acc_out,
+                      max_iterations, flags, ws, stream), "map_detect")
+    r = Result.from_tensor(res)
+    tr = None
+    if trace is not None:
+        tr = trace.cpu().numpy().view(np.uint64)[:min(r.iterations, trace_cap)].copy()
+    return DetectOut(r, tr, acc_out.cpu().numpy() if acc_out is not None else None)

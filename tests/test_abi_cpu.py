@@ -1,0 +1,95 @@
+"""The C-ABI library without a GPU: it loads, exports every declared symbol and
+rejects bad arguments on the host before touching the device (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_0912_2555_amd", "libmapcheck.so")
+HEADER = os.path.join(ROOT, "include", "mapcheck.h")
+
+MAP_OK, MAP_EINVAL, MAP_ERANGE, MAP_ENOSPC = 0, -1, -2, -3
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libmapcheck.so is not built (python -m paper_0912_2555_amd.build)")
+    lib = ctypes.CDLL(LIB)
+    vp, i32, i64, u32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
+    lib.map_workspace_bytes.argtypes = [i32, i64, u32]
+    lib.map_workspace_bytes.restype = sz
+    lib.map_build_csr.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.map_propagate.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, u32, vp, sz, vp]
+    lib.map_detect.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, i32, vp, i32, u32, vp, sz, vp]
+    lib.map_strerror.argtypes = [ctypes.c_int]
+    lib.map_strerror.restype = ctypes.c_char_p
+    return lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(map_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert names == ["map_build_csr", "map_detect", "map_propagate", "map_strerror", "map_workspace_bytes"]
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_header_compiles_as_c():
+    import subprocess
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "t.c")
+        with open(src, "w") as f:
+            f.write('#include "mapcheck.h"\nint main(void){ map_result r; (void)r; '
+                    'return (int)sizeof(map_result) - 32; }\n')
+        subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                               "-o", os.path.join(d, "t"), src])
+        assert subprocess.call([os.path.join(d, "t")]) == 0
+
+
+def test_workspace_bytes(lib):
+    a = lib.map_workspace_bytes(1000, 4000, 0)
+    b = lib.map_workspace_bytes(1 << 20, 1 << 22, 0)
+    assert a > 0 and b > a and b % 256 == 0
+    assert b >= 5 * (1 << 20)  # packed values + working flags
+    assert lib.map_workspace_bytes(0, 10, 0) == 0
+    assert lib.map_workspace_bytes(-5, 10, 0) == 0
+    assert lib.map_workspace_bytes(10, -1, 0) == 0
+    assert lib.map_workspace_bytes(10, 1 << 31, 0) == 0
+
+
+def test_host_side_errors_without_device(lib):
+    fake = ctypes.c_void_p(0x1000)
+    # sizes out of range
+    assert lib.map_build_csr(0, 1, fake, fake, fake, fake, None, None, fake, fake, 1 << 20, None) == MAP_ERANGE
+    assert lib.map_build_csr(5, -1, fake, fake, fake, fake, None, None, fake, fake, 1 << 20, None) == MAP_ERANGE
+    # null pointers
+    assert lib.map_build_csr(5, 3, None, fake, fake, fake, None, None, fake, fake, 1 << 20, None) == MAP_EINVAL
+    assert lib.map_build_csr(5, 3, fake, fake, fake, fake, fake, None, fake, fake, 1 << 20, None) == MAP_EINVAL
+    # workspace too small / misaligned
+    assert lib.map_build_csr(5, 3, fake, fake, fake, fake, None, None, fake, fake, 16, None) == MAP_ENOSPC
+    big = lib.map_workspace_bytes(5, 3, 0)
+    assert lib.map_build_csr(5, 3, fake, fake, fake, fake, None, None, fake, ctypes.c_void_p(0x1004), big,
+                             None) == MAP_ENOSPC
+    assert lib.map_propagate(5, None, fake, None, None, fake, fake, fake, 0, fake, big, None) == MAP_EINVAL
+    assert lib.map_propagate(5, fake, fake, None, None, fake, None, fake, 0, fake, big, None) == MAP_EINVAL
+    assert lib.map_propagate(5, fake, fake, None, None, fake, fake, fake, 0x80, fake, big, None) == MAP_EINVAL
+    assert lib.map_detect(0, fake, fake, None, None, fake, fake, None, 0, None, 0, 0, fake, big, None) == MAP_ERANGE
+    assert lib.map_detect(5, fake, fake, None, None, None, fake, None, 0, None, 0, 0, fake, big, None) == MAP_EINVAL
+    assert lib.map_detect(5, fake, fake, None, None, fake, None, None, 0, None, 0, 0, fake, big, None) == MAP_EINVAL
+    assert lib.map_detect(5, fake, fake, None, None, fake, fake, fake, -1, None, 0, 0, fake, big, None) == MAP_EINVAL
+    assert lib.map_detect(5, fake, fake, None, None, fake, fake, None, 0, None, 0, 0, fake, 8, None) == MAP_ENOSPC
+
+
+def test_strerror(lib):
+    for code in range(-6, 1):
+        assert lib.map_strerror(code).decode()
+    assert lib.map_strerror(99).decode() == "unknown status"

@@ -1,0 +1,294 @@
+"""Parity of the HIP library (through its C ABI) with the CPU oracle.
+
+Integer work: every comparison is bit-exact -- found flag, witness, K, the
+accepting set at exit, per-iteration |Del_k| and map digests, and full map
+vectors where the oracle can produce them.  Sweep counts depend on the
+schedule and are not compared.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def mc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    import paper_0912_2555_amd as mc
+    return mc
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def accepting_sequence(g, ref):
+    """A_1..A_K reconstructed from the oracle's map vectors."""
+    acc = g.acc.copy()
+    out = []
+    for k in range(ref.iterations):
+        out.append(acc.copy())
+        nz = ref.maps[k][ref.maps[k] != 0]
+        acc[nz - 1] = 0
+    return out
+
+
+def check_detect(mc, g, csr=None, max_iterations=0, trace_cap=None, flags=0, ref=None):
+    say("detect", g.name, "n", g.n, "m", g.m)
+    if csr is None:
+        csr = mc.build_csr(g.n, g.src, g.dst)
+    if ref is None:
+        ref = oracle.map_detect(g, mode="desc", max_iterations=max_iterations)
+    cap = (g.n_acc + 1) if trace_cap is None else trace_cap
+    out = mc.detect(csr, g.acc, trace_cap=cap, want_acc=True, max_iterations=max_iterations, flags=flags)
+    r = out.result
+    want_status = 0 if ref.status == 0 else mc.MAP_ENOTCONVERGED
+    assert r.status == want_status, (g.name, r)
+    assert r.verdict == ref.verdict, (g.name, r, ref.verdict)
+    assert r.accepting_left == ref.accepting_left
+    assert np.array_equal(out.accepting_out, ref.acc_out)
+    rows = min(r.iterations, cap)
+    assert out.trace.shape[0] == rows
+    assert np.array_equal(out.trace[:, 0], ref.trace[:rows, 0].astype(np.uint64)), g.name
+    if not flags & mc.MAP_FLAG_NO_TRACE_DIGEST:
+        assert np.array_equal(out.trace[:, 2], ref.trace[:rows, 2].astype(np.uint64)), g.name
+    assert np.all(out.trace[:, 1] >= 1)
+    assert r.sweeps == int(out.trace[:, 1].sum()) or rows < r.iterations
+    return out, ref
+
+
+def check_propagate_all(mc, g, csr=None, max_k=None):
+    """Full map vector of every iteration (the oracle's A_k as input)."""
+    if csr is None:
+        csr = mc.build_csr(g.n, g.src, g.dst)
+    ref = oracle.map_detect(g, mode="jacobi" if g.n <= 20000 else "desc", maps_cap=max_k or (g.n_acc + 1))
+    accs = accepting_sequence(g, ref)
+    for k, acc in enumerate(accs[:max_k]):
+        got, res = mc.propagate(csr, acc)
+        assert res.status == 0
+        assert np.array_equal(got.cpu().numpy(), ref.maps[k]), (g.name, k + 1)
+    return ref
+
+
+# ------------------------------------------------------------------ small
+
+def test_hand_example(mc):
+    from conftest import read_golden
+    gold = read_golden("hand_example.txt")
+    g = synth.from_edges(gold["n"][0][0], [tuple(e) for e in gold["edge"]], gold["accepting"][0], "hand")
+    out, _ = check_detect(mc, g)
+    assert list(out.result.verdict) == gold["result"][0]
+    check_propagate_all(mc, g)
+
+
+@pytest.mark.parametrize("dag", [False, True], ids=["c1a", "c1b"])
+def test_config1_full_vectors(mc, dag):
+    g = synth.config1(dag=dag)
+    csr = mc.build_csr(g.n, g.src, g.dst)
+    check_detect(mc, g, csr)
+    check_propagate_all(mc, g, csr)
+
+
+def _random_cases():
+    cases = []
+    for i, (n, deg) in enumerate([(1, 1), (2, 2), (3, 3), (63, 2), (64, 3), (65, 1), (127, 4), (128, 2),
+                                  (129, 3), (1000, 1.2), (1000, 3), (4099, 2), (20000, 1.1), (40000, 2.5),
+                                  (70001, 1.5)]):
+        m = max(0, int(n * deg))
+        cases.append(synth.random_graph(100 + i, n, m, p_acc=0.05 if n > 100 else 0.3))
+    return cases
+
+
+@pytest.mark.parametrize("g", _random_cases(), ids=lambda g: g.name)
+def test_random_graphs(mc, g):
+    csr = mc.build_csr(g.n, g.src, g.dst)
+    check_detect(mc, g, csr)
+    check_propagate_all(mc, g, csr, max_k=4)
+
+
+@pytest.mark.parametrize("n,planted", [(1 << 14, False), (1 << 14, True), (1 << 16, False), (1 << 16, True)])
+def test_config2_reduced(mc, n, planted):
+    g = synth.config2(seed=2, n=n, planted=planted)
+    csr = mc.build_csr(g.n, g.src, g.dst)
+    _, ref = check_detect(mc, g, csr)
+    if planted:
+        assert ref.found == 1
+
+
+def test_config3_reduced(mc):
+    g = synth.config3(n=1 << 18)
+    csr = mc.build_csr(g.n, g.src, g.dst)
+    check_detect(mc, g, csr)
+    check_propagate_all(mc, g, csr, max_k=2)
+
+
+# ------------------------------------------------------------- edge cases
+
+def test_single_vertex_cases(mc):
+    for edges, acc, want in [([], [], (0, 0, 0)), ([], [1], (0, 0, 1)), ([(1, 1)], [1], (1, 1, 1)),
+                             ([(1, 1)], [], (0, 0, 0))]:
+        g = synth.from_edges(1, edges, acc, f"n1{edges}{acc}")
+        out, _ = check_detect(mc, g)
+        assert out.result.verdict == want
+
+
+def test_no_edges(mc):
+    g = synth.from_edges(300, [], [5, 17, 299], "no-edges")
+    out, _ = check_detect(mc, g)
+    assert out.result.verdict == (0, 0, 1)
+
+
+def test_all_accepting_and_duplicates(mc):
+    rng = np.random.default_rng(3)
+    n = 5000
+    src = rng.integers(1, n + 1, 4000)
+    dst = np.minimum(src + rng.integers(0, 3, 4000), n)
+    src = np.concatenate([src, src[:1000]])  # duplicates
+    dst = np.concatenate([dst, dst[:1000]])
+    g = synth.Graph(n=n, src=src.astype(np.int32), dst=dst.astype(np.int32), acc=np.ones(n, np.uint8), name="allacc")
+    check_detect(mc, g)
+
+
+def test_hub_rows(mc):
+    # one out-hub spanning many LDS chunks, one in-hub, plus a chain
+    n = 200_000
+    rng = np.random.default_rng(4)
+    hub_out = np.stack([np.full(100_000, 7), rng.integers(1, n + 1, 100_000)], 1)
+    hub_in = np.stack([rng.integers(1, n + 1, 50_000), np.full(50_000, 150_000)], 1)
+    chain = np.stack([np.arange(1000, 1500), np.arange(1001, 1501)], 1)
+    e = np.concatenate([hub_out, hub_in, chain]).astype(np.int32)
+    acc = np.zeros(n, np.uint8)
+    acc[rng.choice(n, 300, replace=False)] = 1
+    acc[150_000 - 1] = 1
+    g = synth.Graph(n=n, src=e[:, 0].copy(), dst=e[:, 1].copy(), acc=acc, name="hubs")
+    csr = mc.build_csr(g.n, g.src, g.dst)
+    check_detect(mc, g, csr)
+    check_propagate_all(mc, g, csr, max_k=2)
+
+
+@pytest.mark.parametrize("k", [2, 50, 200])
+def test_increasing_chain(mc, k):
+    g = synth.from_edges(k, [(i, i + 1) for i in range(1, k)], range(1, k + 1), f"chain{k}")
+    out, _ = check_detect(mc, g)
+    assert out.result.verdict == (0, 0, k)
+
+
+def test_star_graphs(mc):
+    n = 10_000
+    out_star = [(1, v) for v in range(2, n + 1)]
+    in_star = [(v, 1) for v in range(2, n + 1)]
+    for edges, name in ((out_star, "out-star"), (in_star, "in-star"), (out_star + [(n, 1)], "star+back")):
+        g = synth.from_edges(n, edges, range(1, n + 1, 97), name)
+        check_detect(mc, g)
+
+
+def test_trace_cap_and_iteration_cap(mc):
+    k = 40
+    g = synth.from_edges(k, [(i, i + 1) for i in range(1, k)], range(1, k + 1), "chain-cap")
+    check_detect(mc, g, trace_cap=5)
+    out, ref = check_detect(mc, g, max_iterations=7)
+    assert out.result.status == mc.MAP_ENOTCONVERGED and out.result.iterations == 7
+
+
+def test_no_digest_flag(mc):
+    g = synth.config1(dag=True)
+    out, _ = check_detect(mc, g, flags=mc.MAP_FLAG_NO_TRACE_DIGEST)
+    assert np.all(out.trace[:, 2] == 0)
+
+
+# ---------------------------------------------------------------- CSR build
+
+def test_csr_build_matches_edge_list(mc):
+    g = synth.config2(seed=5, n=1 << 15, planted=True)
+    csr = mc.build_csr(g.n, g.src, g.dst)
+    assert int(csr.status.item()) == 0
+    for rp, col, key, other in ((csr.row_ptr, csr.col, g.src, g.dst), (csr.rrow_ptr, csr.rcol, g.dst, g.src)):
+        rp = rp.cpu().numpy()
+        col = col.cpu().numpy()[:g.m]
+        deg = np.bincount(key - 1, minlength=g.n)
+        assert rp[0] == 0 and np.array_equal(np.diff(rp), deg)
+        # same multiset of (row, col) pairs
+        rows = np.repeat(np.arange(g.n), deg)
+        got = np.sort(rows.astype(np.int64) * g.n + col)
+        want = np.sort((key.astype(np.int64) - 1) * g.n + (other - 1))
+        assert np.array_equal(got, want)
+
+
+def test_csr_build_range_error(mc):
+    import torch
+    n = 10
+    src = torch.tensor([1, 2, 11], dtype=torch.int32)
+    dst = torch.tensor([2, 3, 1], dtype=torch.int32)
+    csr = mc.build_csr(n, src, dst)
+    torch.cuda.synchronize()
+    assert int(csr.status.item()) == mc.MAP_ERANGE_DEV
+
+
+def test_csr_build_empty(mc):
+    csr = mc.build_csr(5, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert csr.row_ptr.cpu().numpy().tolist() == [0] * 6
+
+
+# ------------------------------------------------------- schedule independence
+
+def test_repeated_runs_identical(mc):
+    g = synth.config2(seed=7, n=1 << 16)
+    csr = mc.build_csr(g.n, g.src, g.dst)
+    first = mc.detect(csr, g.acc, trace_cap=g.n_acc + 1)
+    for _ in range(5):
+        again = mc.detect(csr, g.acc, trace_cap=g.n_acc + 1)
+        assert again.result.verdict == first.result.verdict
+        assert np.array_equal(again.trace[:, [0, 2]], first.trace[:, [0, 2]])
+
+
+# ------------------------------------------------------------------ full size
+
+def _golden(key):
+    path = os.path.join(ROOT, "tests", "golden", "full_size.json")
+    data = json.load(open(path))
+    if key not in data:
+        pytest.fail(f"golden {key} missing: run tests/golden/make_goldens.py")
+    return data[key]
+
+
+def _check_golden(mc, g, gold):
+    import hashlib
+    say("full-size detect", g.name, "m", g.m)
+    assert g.n == gold["n"] and g.m == gold["m"]
+    csr = mc.build_csr(g.n, g.src, g.dst)
+    out = mc.detect(csr, g.acc, trace_cap=g.n_acc + 1, want_acc=True)
+    r = out.result
+    assert r.status == 0
+    assert r.verdict == (gold["found"], gold["witness"], gold["iterations"])
+    assert r.accepting_left == gold["accepting_left"]
+    assert [int(x) for x in out.trace[:, 0]] == gold["dels"]
+    dig = out.trace[:, 2].astype("<u8")
+    assert [f"{int(x):016x}" for x in dig[:8]] == gold["digest_head"]
+    assert hashlib.sha256(dig.tobytes()).hexdigest() == gold["digest_sha256"]
+    return csr, out
+
+
+@pytest.mark.parametrize("key,planted", [("c2B", False), ("c2A", True)])
+def test_config2_full_size(mc, key, planted):
+    g = synth.config2(planted=planted)
+    csr, out = _check_golden(mc, g, _golden(key))
+    # first iteration's full map vector against the oracle's fixpoint
+    got, res = mc.propagate(csr, g.acc)
+    want, _ = oracle.fixpoint(g, mode="desc")
+    assert np.array_equal(got.cpu().numpy(), want)
+
+
+def test_config3_full_size(mc):
+    g = synth.config3()
+    _check_golden(mc, g, _golden("c3"))
