@@ -76,9 +76,6 @@ constexpr size_t kCtrlBytes = 16384;
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ uint32_t ld_acquire(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -128,42 +125,52 @@ struct Grid {
 
 // Grid-wide barrier with a summed 32-bit payload.  Every thread must call it.
 // Returns false if the wait exceeded its bound (the kernel must then exit).
+//
+// Ordering: each block's leader issues one agent-scope release fence before
+// its arrival (cumulative over the block's waves through the workgroup
+// barrier); the last arrival of a group and the last group leader acquire
+// before forwarding; waiters poll with relaxed loads (no cache invalidation
+// per poll) and acquire once when the generation moves.
 __device__ bool grid_sync(Grid& g, uint32_t payload, uint32_t* total) {
   __shared__ uint32_t s_total;
   __shared__ int s_ok;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __syncthreads();
   if (threadIdx.x == 0) {
     Ctrl* c = g.c;
     int ok = 1;
-    unsigned long long inc = (1ull << 32) | payload;
-    unsigned long long old = __hip_atomic_fetch_add(&c->grp[g.group].v, inc, __ATOMIC_ACQ_REL,
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned long long inc = (1ull << 32) | payload;
+    unsigned long long old = __hip_atomic_fetch_add(&c->grp[g.group].v, inc, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
     if ((int)(old >> 32) == g.group_size - 1) {
-      uint32_t gsum = (uint32_t)old + payload;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const uint32_t gsum = (uint32_t)old + payload;
       __hip_atomic_store(&c->grp[g.group].v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      unsigned long long old2 = __hip_atomic_fetch_add(&c->top.v, (1ull << 32) | gsum, __ATOMIC_ACQ_REL,
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      unsigned long long old2 = __hip_atomic_fetch_add(&c->top.v, (1ull << 32) | gsum, __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_AGENT);
       if ((int)(old2 >> 32) == g.ngroups - 1) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __hip_atomic_store(&c->top.v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         st_agent(&c->payload, (uint32_t)old2 + gsum);
         __hip_atomic_store(&c->gen, g.gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
     const uint64_t t0 = wall_clock64();
-    while (ld_acquire(&c->gen) == g.gen) {
+    while (ld_agent(&c->gen) == g.gen) {
       __builtin_amdgcn_s_sleep(1);
       if (wall_clock64() - t0 > kWaitTicks || ld_agent((const uint32_t*)&c->abort)) {
         ok = 0;
         break;
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (!ok) st_agent((uint32_t*)&c->abort, 1u);
     s_total = ok ? ld_agent(&c->payload) : 0u;
     s_ok = ok;
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   // Epoch E+1 writes set (E+1)%3 and reads set E%3; set (E-1)%3 was last read
   // during epoch E, so block 0 clears it now for epoch E+2.
   if (blockIdx.x == 0 && threadIdx.x < kStripes) {
