@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--workload", default="c2B", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--sync-sweeps", action="store_true", help="grid barrier after every sweep")
+    ap.add_argument("--stream", action="store_true", help="stream the CSR every sweep (no on-chip staging)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -116,6 +118,8 @@ def main():
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     res = mc.new_result(dev)
     stream = torch.cuda.current_stream()
+    flags = mc.MAP_FLAG_NO_TRACE_DIGEST | (mc.MAP_FLAG_SYNC_SWEEPS if args.sync_sweeps else 0) | \
+        (mc.MAP_FLAG_STREAM if args.stream else 0)
 
     def step(ev=None):
         rc = mc.map_build_csr(n, src, dst, row_ptr, col, rrow_ptr, rcol, status, ws)
@@ -123,8 +127,7 @@ def main():
             raise mc.MapError(rc, "map_build_csr")
         if ev is not None:
             ev[0].record(stream)
-        rc = mc.map_detect(n, row_ptr, col, rrow_ptr, rcol, acc, res, None, None, 0,
-                           mc.MAP_FLAG_NO_TRACE_DIGEST, ws)
+        rc = mc.map_detect(n, row_ptr, col, rrow_ptr, rcol, acc, res, None, None, 0, flags, ws)
         if rc:
             raise mc.MapError(rc, "map_detect")
         if ev is not None:
@@ -160,7 +163,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload][0], "key": args.workload, "n": n, "m": m,
-                   "accepting": int(g.n_acc), "parallelism": "single GPU"},
+                   "accepting": int(g.n_acc), "parallelism": "single GPU", "flags": flags},
         "result": {"found": r.found, "witness": r.witness, "iterations": k, "sweeps": r.sweeps,
                    "accepting_left": r.accepting_left, "matches_oracle_golden": exact},
         "detect_ms": round(detect_ms, 4), "build_ms": round(ms_step - detect_ms, 4),

@@ -59,6 +59,8 @@ extern "C" {
 /* Flags (bitwise or; 0 = automatic choice). */
 #define MAP_FLAG_DENSE_ONLY 0x1u /* never switch to the sparse (frontier) sweep */
 #define MAP_FLAG_NO_TRACE_DIGEST 0x2u /* leave the digest column of the trace 0 */
+#define MAP_FLAG_STREAM 0x4u /* never stage the CSR in on-chip memory: stream it every sweep */
+#define MAP_FLAG_SYNC_SWEEPS 0x8u /* a grid-wide barrier after every sweep (no asynchronous sweeps) */
 
 /* Result of map_propagate / map_detect, written to device memory (32 bytes). */
 typedef struct map_result {

@@ -40,6 +40,8 @@ MAP_ENOTCONVERGED = -5
 MAP_ERANGE_DEV = -6
 MAP_FLAG_DENSE_ONLY = 0x1
 MAP_FLAG_NO_TRACE_DIGEST = 0x2
+MAP_FLAG_STREAM = 0x4
+MAP_FLAG_SYNC_SWEEPS = 0x8
 
 EXPORTS = ("map_workspace_bytes", "map_build_csr", "map_propagate", "map_detect", "map_strerror")
 

@@ -31,17 +31,26 @@
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kBlock = 512;  // threads per workgroup of the loop kernel
+constexpr int kBlock = 1024;  // threads per workgroup of the loop kernel (one per CU)
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kTileRows = 128;    // rows per wave tile
-constexpr int kTileEdges = 1024;  // edges staged in LDS per wave (4 KiB)
+constexpr int kTileEdges = 512;   // stream mode: edges staged in LDS per wave (2 KiB)
 constexpr int kRowsPerLane = kTileRows / kWave;
 constexpr int kEdgesPerLane = kTileEdges / kWave;
+constexpr int kResRowsPerLane = 4;                     // resident mode: rows per lane
+constexpr int kResWaveRows = kWave * kResRowsPerLane;  // resident mode: rows per wave
+constexpr int kResEdges = 24576;                        // resident mode: CSR edges per block in LDS
+constexpr int kGatherBatch = 12;                        // resident mode: gathers in flight per lane
+constexpr int kSortSlots = 1024;                        // resident mode: bitonic sort width (>= 64 * kGatherBatch)
+constexpr int kSortPerLane = kSortSlots / kWave;
+static_assert(kSortSlots >= kWave * kGatherBatch, "sort must cover a gather batch");
+constexpr uint32_t kAllFlags = MAP_FLAG_DENSE_ONLY | MAP_FLAG_NO_TRACE_DIGEST | MAP_FLAG_STREAM | MAP_FLAG_SYNC_SWEEPS;
 constexpr uint32_t kAccBit = 0x80000000u;
 constexpr uint32_t kValMask = 0x7fffffffu;
 constexpr int kStripes = 16;
 constexpr int kSets = 3;
 constexpr int kMaxGroups = 8;  // barrier arrival groups (one per XCD)
+constexpr int kMaxBlocks = 2048;  // upper bound on the loop kernel's grid
 // Bound on one barrier wait, in ticks of the 100 MHz device wall clock (10 s):
 // far beyond any legitimate phase, so a broken launch exits instead of hanging.
 constexpr uint64_t kWaitTicks = 1000000000ull;
@@ -69,9 +78,16 @@ struct Ctrl {
   int32_t abort;                   // set when a barrier wait exceeded its bound
   uint32_t pad0[29];
   Stripe sets[kSets][kStripes];    // per-epoch reductions
+  // Asynchronous fixpoint: change counter, per-block quiet reports
+  // {iteration, counter + 1} and the iteration whose fixpoint is established.
+  alignas(128) uint32_t dirty;
+  uint32_t pad1[31];
+  alignas(128) uint32_t done;
+  uint32_t pad2[31];
+  unsigned long long quiet[kMaxBlocks];
 };
-static_assert(sizeof(Ctrl) <= 16384, "ctrl block too large");
-constexpr size_t kCtrlBytes = 16384;
+constexpr size_t kCtrlBytes = 32768;
+static_assert(sizeof(Ctrl) <= kCtrlBytes, "ctrl block too large");
 
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -204,12 +220,49 @@ struct LoopArgs {
   int32_t max_iter;
   int32_t propagate;  // 1: one fixpoint of acc_in, write map_out
   int32_t digest;     // 1: compute the trace digest
+  int32_t force_stream;  // 1: never stage the CSR in LDS
+  int32_t sync_sweeps;   // 1: a grid barrier after every sweep instead of the asynchronous fixpoint
 };
 
+// Row ownership: the rows are cut into one contiguous range per block and,
+// inside it, one contiguous range per wave.  A wave is the only writer of the
+// packed values of its rows for the whole launch.
+//
+// Two sweep modes, chosen per block at launch:
+//   resident  the block's slice of the CSR (column indices plus, per edge, the
+//             row's offset inside its wave) is staged in LDS once; the wave's
+//             packed values live in registers; a sweep is one batch of gathers
+//             per lane, reduced per row with LDS atomic max.
+//   stream    row offsets and column indices are streamed from HBM in tiles of
+//             kTileRows rows, gathered values staged in LDS, reduced per row.
 struct TileLds {
   int32_t rp[kTileRows + 1];
   uint32_t val[kTileEdges];
 };
+
+struct ResLds {
+  int32_t col[kResEdges];
+  uint8_t roff[kResEdges];
+  uint32_t best[kWavesPerBlock][kResWaveRows];
+};
+
+union BlockLds {
+  TileLds tile[kWavesPerBlock];
+  ResLds res;
+};
+
+struct WaveRows {
+  int64_t r0, r1;  // rows of this wave
+  int32_t we0, we1;  // resident: edge range of the wave inside the block's LDS slice
+  bool resident;
+  uint32_t own[kResRowsPerLane];  // resident: packed values of rows r0 + lane + 64 j
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Value that successor w (0-based) sends along an edge: its map value, or its
 // own id if it is accepting and larger.
@@ -219,30 +272,31 @@ __device__ __forceinline__ uint32_t sent_packed(uint32_t x, int32_t w) {
   return (x & kAccBit) ? (m > id ? m : id) : m;
 }
 
-// One tile of a sweep, processed by one wave.  first != 0: the sweep that
-// starts an iteration from map = 0; successors send their id if accepting
-// (read from acc) and every row's packed value is written.  Otherwise rows
-// pull the packed values of their successors and a row is written only when
+// What successor w sends in the first sweep of an iteration (map = 0 everywhere).
+__device__ __forceinline__ uint32_t sent_first(const uint8_t* acc, int32_t w) {
+  return acc[w] ? (uint32_t)w + 1u : 0u;
+}
+
+// Stream mode, rows [r0, r1) with r1 - r0 <= kTileRows, processed by one wave.
+// kFirst: the sweep that starts an iteration from map = 0 (successors send their
+// id if accepting, every row is written).  Otherwise a row is written only when
 // its value grows.  Returns nonzero (wave-uniform) if some row changed.
 template <bool kFirst>
-__device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int tile, TileLds& L, int lane,
+__device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int64_t r0, int64_t r1, TileLds& L, int lane,
                                uint32_t* acc_count) {
-  const int64_t r0 = (int64_t)tile * kTileRows;
-  const int64_t r1 = min((int64_t)a.n, r0 + kTileRows);
   const int nr = (int)(r1 - r0);
   for (int i = lane; i <= nr; i += kWave) L.rp[i] = __builtin_nontemporal_load(a.row_ptr + r0 + i);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  wave_lds_sync();
   const int32_t e0 = L.rp[0], e1 = L.rp[nr];
   int32_t lo[kRowsPerLane], hi[kRowsPerLane];
-  uint32_t best[kRowsPerLane];
+  uint32_t best[kRowsPerLane], old[kRowsPerLane];
 #pragma unroll
   for (int j = 0; j < kRowsPerLane; ++j) {
     int r = lane + j * kWave;
     lo[j] = r < nr ? L.rp[r] : 0;
     hi[j] = r < nr ? L.rp[r + 1] : 0;
     best[j] = 0;
+    old[j] = (!kFirst && r < nr) ? a.pv[r0 + r] : 0u;
   }
   for (int32_t c0 = e0; c0 < e1; c0 += kTileEdges) {
     const int cnt = (int)min((int64_t)kTileEdges, (int64_t)e1 - c0);
@@ -255,16 +309,11 @@ __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int tile, 
 #pragma unroll
     for (int u = 0; u < kEdgesPerLane; ++u) {
       int i = lane + u * kWave;
-      uint32_t s = 0;
-      if ((uint32_t)w[u] < (uint32_t)a.n) {
-        if (kFirst) s = acc[w[u]] ? (uint32_t)w[u] + 1u : 0u;
-        else s = sent_packed(a.pv[w[u]], w[u]);
-      }
-      if (i < cnt) L.val[i] = s;
+      uint32_t x = 0;
+      if ((uint32_t)w[u] < (uint32_t)a.n) x = kFirst ? sent_first(acc, w[u]) : sent_packed(a.pv[w[u]], w[u]);
+      if (i < cnt) L.val[i] = x;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_lds_sync();
 #pragma unroll
     for (int j = 0; j < kRowsPerLane; ++j) {
       int b = max(lo[j] - c0, 0), e = min(hi[j] - c0, cnt);
@@ -272,9 +321,7 @@ __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int tile, 
       for (int k = b; k < e; ++k) m = max(m, L.val[k]);
       best[j] = m;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_lds_sync();
   }
   uint32_t changed = 0, nacc = 0;
 #pragma unroll
@@ -287,12 +334,9 @@ __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int tile, 
         nacc += isacc;
         a.pv[v] = (isacc << 31) | best[j];
         changed |= best[j] != 0;
-      } else {
-        uint32_t old = a.pv[v];
-        if (best[j] > (old & kValMask)) {
-          a.pv[v] = (old & kAccBit) | best[j];
-          changed = 1;
-        }
+      } else if (best[j] > (old[j] & kValMask)) {
+        a.pv[v] = (old[j] & kAccBit) | best[j];
+        changed = 1;
       }
     }
   }
@@ -300,8 +344,140 @@ __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int tile, 
   return __ballot(changed) != 0;
 }
 
+// Resident mode: one sweep over the wave's rows from its LDS slice.
+template <bool kFirst>
+__device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, WaveRows& W, ResLds& R, int wib,
+                                   int lane, uint32_t* acc_count) {
+  uint32_t* best = R.best[wib];
+#pragma unroll
+  for (int j = 0; j < kResRowsPerLane; ++j) best[lane + j * kWave] = 0;
+  wave_lds_sync();
+  for (int32_t k0 = W.we0; k0 < W.we1; k0 += kWave * kGatherBatch) {
+    int32_t w[kGatherBatch];
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u) {
+      int32_t k = k0 + lane + u * kWave;
+      w[u] = k < W.we1 ? R.col[k] : -1;
+    }
+    uint32_t x[kGatherBatch];
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u) {
+      x[u] = 0;
+      if ((uint32_t)w[u] < (uint32_t)a.n) x[u] = kFirst ? sent_first(acc, w[u]) : sent_packed(a.pv[w[u]], w[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u) {
+      int32_t k = k0 + lane + u * kWave;
+      if (k < W.we1 && x[u] != 0) atomicMax(&best[R.roff[k]], x[u]);
+    }
+  }
+  wave_lds_sync();
+  uint32_t changed = 0, nacc = 0;
+#pragma unroll
+  for (int j = 0; j < kResRowsPerLane; ++j) {
+    int64_t v = W.r0 + lane + j * kWave;
+    if (v < W.r1) {
+      uint32_t b = best[lane + j * kWave];
+      if (kFirst) {
+        uint32_t isacc = acc[v] ? 1u : 0u;
+        nacc += isacc;
+        W.own[j] = (isacc << 31) | b;
+        a.pv[v] = W.own[j];
+        changed |= b != 0;
+      } else if (b > (W.own[j] & kValMask)) {
+        W.own[j] = (W.own[j] & kAccBit) | b;
+        a.pv[v] = W.own[j];
+        changed = 1;
+      }
+    }
+  }
+  if (acc_count) *acc_count += nacc;
+  return __ballot(changed) != 0;
+}
+
+template <bool kFirst>
+__device__ uint32_t sweep_rows(const LoopArgs& a, const uint8_t* acc, WaveRows& W, BlockLds& S, int wib, int lane,
+                               uint32_t* acc_count) {
+  if (W.resident) return sweep_resident<kFirst>(a, acc, W, S.res, wib, lane, acc_count);
+  uint32_t ch = 0;
+  if (W.r1 > W.r0) {
+    // Tiles in decreasing row order: values mostly flow from high ids to low.
+    for (int64_t t0 = W.r0 + ((W.r1 - W.r0 - 1) / kTileRows) * kTileRows; t0 >= W.r0; t0 -= kTileRows)
+      ch |= sweep_tile<kFirst>(a, acc, t0, min(W.r1, t0 + kTileRows), S.tile[wib], lane, acc_count);
+  }
+  return ch;
+}
+
+// Calls f(v, packed value of v) for every row v of the wave (lane-strided).
+template <typename F>
+__device__ __forceinline__ void for_own_rows(const LoopArgs& a, const WaveRows& W, int lane, F f) {
+  if (W.resident) {
+#pragma unroll
+    for (int j = 0; j < kResRowsPerLane; ++j) {
+      int64_t v = W.r0 + lane + j * kWave;
+      if (v < W.r1) f(v, W.own[j]);
+    }
+  } else {
+    for (int64_t v = W.r0 + lane; v < W.r1; v += kWave) f(v, a.pv[v]);
+  }
+}
+
+// Resident mode set-up: sort each gather batch of the wave's edges by target
+// (key = target << 8 | row offset), so that the 64 lanes of one gather
+// instruction read neighbouring addresses and touch few cache lines.  Bitonic
+// network over kSortSlots keys held kSortSlots / 64 per lane (element i lives
+// in lane i % 64, slot i / 64); padding keys are 0xffffffff and sort last.
+__device__ void sort_gather_batches(ResLds& R, int32_t we0, int32_t we1, int lane) {
+  for (int32_t k0 = we0; k0 < we1; k0 += kWave * kGatherBatch) {
+    const int cnt = (int)min((int32_t)(kWave * kGatherBatch), we1 - k0);
+    uint32_t key[kSortPerLane];
+#pragma unroll
+    for (int u = 0; u < kSortPerLane; ++u) {
+      const int i = lane + u * kWave;
+      key[u] = i < cnt ? ((uint32_t)R.col[k0 + i] << 8) | R.roff[k0 + i] : 0xffffffffu;
+    }
+#pragma unroll
+    for (int k = 2; k <= kSortSlots; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        if (j >= kWave) {
+          const int ju = j / kWave;
+#pragma unroll
+          for (int u = 0; u < kSortPerLane; ++u) {
+            if (u & ju) continue;
+            const int i = lane + u * kWave;
+            const bool asc = (i & k) == 0;
+            const uint32_t x = key[u], y = key[u | ju];
+            const bool sw = asc ? (x > y) : (x < y);
+            key[u] = sw ? y : x;
+            key[u | ju] = sw ? x : y;
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < kSortPerLane; ++u) {
+            const int i = lane + u * kWave;
+            const uint32_t y = (uint32_t)__shfl_xor((int)key[u], j, kWave);
+            const bool asc = (i & k) == 0;
+            const bool lower = (i & j) == 0;
+            const uint32_t lo = min(key[u], y), hi = max(key[u], y);
+            key[u] = (lower == asc) ? lo : hi;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSortPerLane; ++u) {
+      const int i = lane + u * kWave;
+      if (i < cnt) {
+        R.col[k0 + i] = (int32_t)(key[u] >> 8);
+        R.roff[k0 + i] = (uint8_t)(key[u] & 0xffu);
+      }
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) map_loop_kernel(LoopArgs a) {
-  __shared__ TileLds lds[kWavesPerBlock];
+  __shared__ BlockLds S;
   __shared__ uint32_t s_red[kWavesPerBlock];
   __shared__ unsigned long long s_red64[kWavesPerBlock];
   __shared__ int32_t s_wit[kWavesPerBlock];
@@ -313,12 +489,39 @@ __global__ void __launch_bounds__(kBlock) map_loop_kernel(LoopArgs a) {
   // XCD-aware numbering: consecutive hardware block ids land on different
   // XCDs; give each XCD a contiguous range of logical blocks (and rows).
   const int logical = (nb % kMaxGroups == 0) ? (b % kMaxGroups) * (nb / kMaxGroups) + b / kMaxGroups : b;
-  const int nwaves = nb * kWavesPerBlock;
-  const int gw = logical * kWavesPerBlock + wib;
-  const int per = (a.ntiles + nwaves - 1) / nwaves;
-  const int t_begin = min(a.ntiles, gw * per);
-  const int t_end = min(a.ntiles, t_begin + per);
-  TileLds& L = lds[wib];
+
+  // Row ranges of this block and wave.
+  const int64_t rows_per_block = ((int64_t)a.n + nb - 1) / nb;
+  const int64_t rb0 = min((int64_t)a.n, (int64_t)logical * rows_per_block);
+  const int64_t rb1 = min((int64_t)a.n, rb0 + rows_per_block);
+  const int64_t rows_per_wave = (rows_per_block + kWavesPerBlock - 1) / kWavesPerBlock;
+  WaveRows W;
+  W.r0 = min(rb1, rb0 + (int64_t)wib * rows_per_wave);
+  W.r1 = min(rb1, W.r0 + rows_per_wave);
+  W.we0 = W.we1 = 0;
+#pragma unroll
+  for (int j = 0; j < kResRowsPerLane; ++j) W.own[j] = 0;
+  {
+    const int32_t eb0 = a.row_ptr[rb0], eb1 = a.row_ptr[rb1];
+    W.resident = !a.force_stream && a.n <= (1 << 24) && rows_per_wave <= kResWaveRows &&
+                 (int64_t)eb1 - eb0 <= kResEdges;
+    if (W.resident) {
+      // Stage the block's column slice and each edge's row offset in its wave.
+      for (int32_t k = threadIdx.x; k < eb1 - eb0; k += kBlock) S.res.col[k] = a.col[eb0 + k];
+      for (int64_t r = rb0 + threadIdx.x; r < rb1; r += kBlock) {
+        const uint8_t off = (uint8_t)((r - rb0) % rows_per_wave);
+        const int32_t k1 = a.row_ptr[r + 1] - eb0;
+        for (int32_t k = a.row_ptr[r] - eb0; k < k1; ++k) S.res.roff[k] = off;
+      }
+      W.we0 = a.row_ptr[W.r0] - eb0;
+      W.we1 = a.row_ptr[W.r1] - eb0;
+    }
+    __syncthreads();
+    if (W.resident) {
+      sort_gather_batches(S.res, W.we0, W.we1, lane);
+      __syncthreads();
+    }
+  }
 
   Grid g;
   g.c = a.ctrl;
@@ -350,26 +553,32 @@ __global__ void __launch_bounds__(kBlock) map_loop_kernel(LoopArgs a) {
     for (int i = 0; i < kStripes; ++i) t += ld_agent(&c->sets[set][i].count);
     return t;
   };
+  // Any wave of the block changed a row: one flag per block for the barrier.
+  auto block_any = [&](uint32_t ch) {
+    if (lane == 0) s_red[wib] = ch;
+    __syncthreads();
+    uint32_t any = 0;
+    for (int i = 0; i < kWavesPerBlock; ++i) any |= s_red[i];
+    __syncthreads();
+    return any ? 1u : 0u;
+  };
 
   uint32_t count_prev = 0;  // |A_k| of the current iteration
   int32_t k = 0;
   int64_t total_sweeps = 0;
   int32_t status = MAP_OK, found = 0, witness = 0;
   int32_t left = 0;
-  bool acc_from_pv = false;  // acc_out comes from the accepting bits of pv
+  bool acc_from_pv = false;  // acc_out comes from the accepting bits of the packed values
   bool ok = true;
   uint32_t tot = 0;
 
   if (!a.propagate) {
     // A_1 -> working flags; count |A_1|.
     uint32_t cnt = 0;
-    for (int t = t_begin; t < t_end; ++t) {
-      int64_t r0 = (int64_t)t * kTileRows, r1 = min((int64_t)a.n, r0 + kTileRows);
-      for (int64_t v = r0 + lane; v < r1; v += kWave) {
-        uint8_t x = a.acc_in[v] ? 1 : 0;
-        a.accw[v] = x;
-        cnt += x;
-      }
+    for (int64_t v = W.r0 + lane; v < W.r1; v += kWave) {
+      uint8_t x = a.acc_in[v] ? 1 : 0;
+      a.accw[v] = x;
+      cnt += x;
     }
     block_add_count(cnt, g.gen % kSets);
     ok = grid_sync(g, 0, nullptr);
@@ -380,14 +589,10 @@ __global__ void __launch_bounds__(kBlock) map_loop_kernel(LoopArgs a) {
 
   for (;;) {
     // First sweep of an iteration: map from 0, accepting flags from acc.
-    uint32_t nacc = 0, ch = 0;
-    for (int t = t_end - 1; t >= t_begin; --t) ch |= sweep_tile<true>(a, acc, t, L, lane, &nacc);
+    uint32_t nacc = 0;
+    uint32_t ch = sweep_rows<true>(a, acc, W, S, wib, lane, &nacc);
     if (!a.propagate) block_add_count(nacc, g.gen % kSets);
-    if (lane == 0) s_red[wib] = ch;
-    __syncthreads();
-    uint32_t bch = 0;
-    for (int i = 0; i < kWavesPerBlock; ++i) bch |= s_red[i];
-    ok = grid_sync(g, bch ? 1u : 0u, &tot);
+    ok = grid_sync(g, block_any(ch), &tot);
     if (!ok) goto aborted;
     if (!a.propagate) {
       uint32_t cnt = read_count((g.gen - 1) % kSets);
@@ -402,42 +607,101 @@ __global__ void __launch_bounds__(kBlock) map_loop_kernel(LoopArgs a) {
     }
     k++;
     int64_t s = 1;
-    while (tot != 0) {
-      if (s > (int64_t)a.n + 1) { status = MAP_ENOTCONVERGED; break; }
-      uint32_t c2 = 0;
-      for (int t = t_end - 1; t >= t_begin; --t) c2 |= sweep_tile<false>(a, acc, t, L, lane, nullptr);
-      if (lane == 0) s_red[wib] = c2;
-      __syncthreads();
-      bch = 0;
-      for (int i = 0; i < kWavesPerBlock; ++i) bch |= s_red[i];
-      s++;
-      ok = grid_sync(g, bch ? 1u : 0u, &tot);
-      if (!ok) goto aborted;
+    if (a.sync_sweeps) {
+      while (tot != 0) {
+        if (s > (int64_t)a.n + 1) { status = MAP_ENOTCONVERGED; break; }
+        uint32_t c2 = sweep_rows<false>(a, acc, W, S, wib, lane, nullptr);
+        s++;
+        ok = grid_sync(g, block_any(c2), &tot);
+        if (!ok) goto aborted;
+      }
+    } else if (tot != 0) {
+      // Asynchronous fixpoint.  Blocks sweep their rows without waiting for one
+      // another; values only grow, so reads of stale remote values are safe.
+      // A sweep that changed something releases its writes and bumps `dirty`;
+      // a sweep that changed nothing, started after reading dirty == d (then an
+      // acquire), reports quiet {k, d+1}.  When every block reports quiet for
+      // the current value of `dirty`, no change happened while any of those
+      // sweeps ran and every change before them was visible to them, so all
+      // rows are at the fixpoint: block 0 then publishes done = k.
+      const uint32_t tag = (uint32_t)(a.propagate ? 1 : k);
+      uint32_t d_seen = 0xffffffffu;  // counter value of this block's last quiet sweep (wave 0)
+      int64_t local = 1;
+      for (;;) {
+        if (wib == 0) {
+          uint32_t cmd = 0, d0 = 0;  // 0 sweep, 1 done, 2 abort
+          const uint64_t t0 = wall_clock64();
+          for (;;) {
+            if (ld_agent(&c->done) == tag) { cmd = 1; break; }
+            const uint32_t d = ld_agent(&c->dirty);
+            if (d != d_seen) { cmd = 0; d0 = d; break; }
+            if (b == 0) {
+              const unsigned long long want = ((unsigned long long)tag << 32) | (uint32_t)(d + 1u);
+              bool mine = true;
+              for (int i = lane; i < nb; i += kWave)
+                mine &= __hip_atomic_load(&c->quiet[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want;
+              if (__ballot(!mine) == 0 && ld_agent(&c->dirty) == d) {
+                if (lane == 0) __hip_atomic_store(&c->done, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                cmd = 1;
+                break;
+              }
+            }
+            if (wall_clock64() - t0 > kWaitTicks || ld_agent((const uint32_t*)&c->abort)) { cmd = 2; break; }
+            __builtin_amdgcn_s_sleep(1);
+          }
+          if (lane == 0) {
+            if (cmd == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (cmd == 2) st_agent((uint32_t*)&c->abort, 1u);
+            s_red[0] = cmd;
+            s_red[1] = d0;
+          }
+        }
+        __syncthreads();
+        const uint32_t cmd = s_red[0], d0 = s_red[1];
+        __syncthreads();
+        if (cmd == 2) goto aborted;
+        if (cmd == 1) break;
+        const uint32_t c2 = sweep_rows<false>(a, acc, W, S, wib, lane, nullptr);
+        local++;
+        const uint32_t any = block_any(c2);
+        if (threadIdx.x == 0) {
+          if (any) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(&c->dirty, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } else {
+            __hip_atomic_store(&c->quiet[b], ((unsigned long long)tag << 32) | (uint32_t)(d0 + 1u),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+        if (wib == 0) d_seen = any ? 0xffffffffu : d0;
+        if (local > 4 * (int64_t)a.n + 16) {  // unreachable for a monotone fixpoint: safety net
+          if (threadIdx.x == 0) st_agent((uint32_t*)&c->abort, 1u);
+          goto aborted;
+        }
+      }
+      s = local;
     }
     total_sweeps += s;
     if (status != MAP_OK) { left = (int32_t)count_prev; acc_from_pv = !a.propagate; break; }
     if (a.propagate) break;
 
     // Detect and strip: witness = max v with map(v) == v; every nonzero map
-    // value loses its accepting flag (the flags of this iteration stay in pv).
+    // value loses its accepting flag (the flags of this iteration stay in the
+    // packed values).
     {
       int32_t wit = 0;
       unsigned long long dig = 0;
-        for (int t = t_begin; t < t_end; ++t) {
-        int64_t r0 = (int64_t)t * kTileRows, r1 = min((int64_t)a.n, r0 + kTileRows);
-        for (int64_t v = r0 + lane; v < r1; v += kWave) {
-          uint32_t mv = a.pv[v] & kValMask;
-          uint32_t id = (uint32_t)v + 1u;
-          if (mv == id) wit = max(wit, (int32_t)id);
-          if (a.digest) dig += mix64(((unsigned long long)id << 32) | mv);
-          if (mv != 0) {
-            // Many vertices share a map value: read before writing.
-            if (acc[mv - 1]) acc[mv - 1] = 0;
-          }
-        }
-      }
+      const bool want_digest = a.digest != 0;
+      for_own_rows(a, W, lane, [&](int64_t v, uint32_t x) {
+        uint32_t mv = x & kValMask;
+        uint32_t id = (uint32_t)v + 1u;
+        if (mv == id) wit = max(wit, (int32_t)id);
+        if (want_digest) dig += mix64(((unsigned long long)id << 32) | mv);
+        // Many vertices share a map value: read before writing.
+        if (mv != 0 && acc[mv - 1]) acc[mv - 1] = 0;
+      });
       wit = wave_max_i32(wit);
-      if (a.digest) dig = wave_sum_u64(dig);
+      if (want_digest) dig = wave_sum_u64(dig);
       if (lane == 0) { s_wit[wib] = wit; s_red64[wib] = dig; }
       __syncthreads();
       if (threadIdx.x == 0) {
@@ -461,7 +725,7 @@ __global__ void __launch_bounds__(kBlock) map_loop_kernel(LoopArgs a) {
         uint64_t* row = a.trace + (int64_t)(k - 1) * 3;
         row[0] = 0;
         row[1] = (uint64_t)s;
-        row[2] = a.digest ? d2 : 0ull;
+        row[2] = want_digest ? d2 : 0ull;
       }
       if (w2 > 0) {
         found = 1;
@@ -476,17 +740,12 @@ __global__ void __launch_bounds__(kBlock) map_loop_kernel(LoopArgs a) {
 done:
   // Outputs: map vector (propagate) or the accepting set at exit (detect).
   if (a.propagate && a.map_out) {
-    for (int t = t_begin; t < t_end; ++t) {
-      int64_t r0 = (int64_t)t * kTileRows, r1 = min((int64_t)a.n, r0 + kTileRows);
-      for (int64_t v = r0 + lane; v < r1; v += kWave) a.map_out[v] = (int32_t)(a.pv[v] & kValMask);
-    }
+    for_own_rows(a, W, lane, [&](int64_t v, uint32_t x) { a.map_out[v] = (int32_t)(x & kValMask); });
   }
   if (!a.propagate && a.acc_out) {
-    for (int t = t_begin; t < t_end; ++t) {
-      int64_t r0 = (int64_t)t * kTileRows, r1 = min((int64_t)a.n, r0 + kTileRows);
-      for (int64_t v = r0 + lane; v < r1; v += kWave)
-        a.acc_out[v] = acc_from_pv ? (uint8_t)(a.pv[v] >> 31) : a.accw[v];
-    }
+    for_own_rows(a, W, lane, [&](int64_t v, uint32_t x) {
+      a.acc_out[v] = acc_from_pv ? (uint8_t)(x >> 31) : a.accw[v];
+    });
   }
   if (b == 0 && threadIdx.x == 0) {
     a.result->found = found;
@@ -678,9 +937,10 @@ int launch_loop(LoopArgs& a, hipStream_t stream) {
   int rc = device_info(&di);
   if (rc) return rc;
   if (!di.coop) return MAP_EDEVICE;
-  const int64_t need = ((int64_t)a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int64_t need = ((int64_t)a.n + (int64_t)kWavesPerBlock * kTileRows - 1) / ((int64_t)kWavesPerBlock * kTileRows);
   int64_t grid = (int64_t)di.cus * di.blocks_per_cu;
   if (grid > need) grid = need;
+  if (grid > kMaxBlocks) grid = kMaxBlocks;
   if (grid >= kMaxGroups) grid -= grid % kMaxGroups;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(fill_u32, dim3(8), dim3(256), 0, stream, reinterpret_cast<uint32_t*>(a.ctrl),
@@ -768,12 +1028,14 @@ int map_propagate(int32_t n, const int32_t* row_ptr, const int32_t* col, const i
                   size_t ws_bytes, void* stream) {
   (void)rrow_ptr;
   (void)rcol;
-  if (flags & ~(MAP_FLAG_DENSE_ONLY | MAP_FLAG_NO_TRACE_DIGEST)) return MAP_EINVAL;
+  if (flags & ~kAllFlags) return MAP_EINVAL;
   if (!map_out) return MAP_EINVAL;
   LoopArgs a;
   int rc = loop_common(n, row_ptr, col, accepting, result, ws, ws_bytes, a);
   if (rc) return rc;
   a.propagate = 1;
+  a.force_stream = (flags & MAP_FLAG_STREAM) ? 1 : 0;
+  a.sync_sweeps = (flags & MAP_FLAG_SYNC_SWEEPS) ? 1 : 0;
   a.map_out = map_out;
   return launch_loop(a, reinterpret_cast<hipStream_t>(stream));
 }
@@ -784,7 +1046,7 @@ int map_detect(int32_t n, const int32_t* row_ptr, const int32_t* col, const int3
                void* stream) {
   (void)rrow_ptr;
   (void)rcol;
-  if (flags & ~(MAP_FLAG_DENSE_ONLY | MAP_FLAG_NO_TRACE_DIGEST)) return MAP_EINVAL;
+  if (flags & ~kAllFlags) return MAP_EINVAL;
   if (trace && trace_cap < 0) return MAP_EINVAL;
   LoopArgs a;
   int rc = loop_common(n, row_ptr, col, accepting0, result, ws, ws_bytes, a);
@@ -795,6 +1057,8 @@ int map_detect(int32_t n, const int32_t* row_ptr, const int32_t* col, const int3
   a.acc_out = accepting_out;
   a.max_iter = max_iterations;
   a.digest = (trace && !(flags & MAP_FLAG_NO_TRACE_DIGEST)) ? 1 : 0;
+  a.force_stream = (flags & MAP_FLAG_STREAM) ? 1 : 0;
+  a.sync_sweeps = (flags & MAP_FLAG_SYNC_SWEEPS) ? 1 : 0;
   return launch_loop(a, reinterpret_cast<hipStream_t>(stream));
 }
 

@@ -117,6 +117,17 @@ def test_random_graphs(mc, g):
     check_propagate_all(mc, g, csr, max_k=4)
 
 
+@pytest.mark.parametrize("g", [c for c in _random_cases() if c.n >= 64] + [synth.config1(dag=True),
+                               synth.config2(seed=3, n=1 << 15, planted=True)], ids=lambda g: g.name)
+def test_stream_mode(mc, g):
+    """The same results with the CSR streamed every sweep instead of staged on chip."""
+    csr = mc.build_csr(g.n, g.src, g.dst)
+    check_detect(mc, g, csr, flags=mc.MAP_FLAG_STREAM)
+    ref = oracle.map_detect(g, mode="desc", maps_cap=1)
+    got, res = mc.propagate(csr, g.acc, flags=mc.MAP_FLAG_STREAM)
+    assert res.status == 0 and np.array_equal(got.cpu().numpy(), ref.maps[0])
+
+
 @pytest.mark.parametrize("n,planted", [(1 << 14, False), (1 << 14, True), (1 << 16, False), (1 << 16, True)])
 def test_config2_reduced(mc, n, planted):
     g = synth.config2(seed=2, n=n, planted=planted)
@@ -131,6 +142,19 @@ def test_config3_reduced(mc):
     csr = mc.build_csr(g.n, g.src, g.dst)
     check_detect(mc, g, csr)
     check_propagate_all(mc, g, csr, max_k=2)
+
+
+@pytest.mark.parametrize("g", [c for c in _random_cases() if c.n >= 64] + [synth.config1(), synth.config1(dag=True),
+                               synth.config2(seed=4, n=1 << 15)], ids=lambda g: g.name)
+@pytest.mark.parametrize("mode", ["sync", "sync+stream"])
+def test_barrier_per_sweep(mc, g, mode):
+    """The same results with a grid barrier after every sweep (no asynchronous sweeps)."""
+    flags = mc.MAP_FLAG_SYNC_SWEEPS | (mc.MAP_FLAG_STREAM if "stream" in mode else 0)
+    csr = mc.build_csr(g.n, g.src, g.dst)
+    check_detect(mc, g, csr, flags=flags)
+    ref = oracle.map_detect(g, mode="desc", maps_cap=1)
+    got, res = mc.propagate(csr, g.acc, flags=flags)
+    assert res.status == 0 and np.array_equal(got.cpu().numpy(), ref.maps[0])
 
 
 # ------------------------------------------------------------- edge cases
