@@ -39,6 +39,11 @@ WORKLOADS = {
     "c1a": ("config 1: N=10,000 uniform digraph, out-degree U{1..4}, 5% accepting", "config1", False),
     "c1b": ("config 1 DAG instance: high->low edges of the config-1 draw", "config1", True),
     "c3": ("config 3: N=2^25 DAG, ~134M edges, 0.1% accepting, no accepting cycle", "config3", None),
+    "c5": ("config 5: Poisson stream of config-1 DAG queries, N log-uniform in [1e4,4e6], accepting ratio "
+           "U[0.1%,5%], odd ones planted; continuous batching under a 32 GiB HBM budget vs a serial plain loop",
+           "config5", None),
+    "c4": ("config 4: 4,096 independent config-1 DAG graphs, N log-uniform in [1e3,1e6], odd ones with a "
+           "planted accepting 64-cycle, one persistent launch vs the plain per-graph loop", "config4", None),
 }
 
 
@@ -83,6 +88,184 @@ def cpu_baseline(g, key, budget_s=20.0):
     }
 
 
+def bench_batch(args):
+    """Batched MAP over the config-4 graphs: graphs/s batched vs the plain loop."""
+    import torch
+    import paper_0912_2555_amd as mc
+    from paper_0912_2555_amd import autotune
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    count = args.batch_count
+    t0 = time.perf_counter()
+    csrs, accs, ns, ms = [], [], [], []
+    ws = None
+    for i in range(count):
+        g = synth.config4(i)
+        if ws is None or ws.numel() < mc.map_workspace_bytes(g.n, g.m):
+            ws = mc.workspace(max(g.n, 1 << 20), max(g.m, 1 << 22), device=dev)
+        csrs.append(mc.build_csr(g.n, g.src, g.dst, transposed=False, ws=ws))
+        accs.append(torch.from_numpy(g.acc).to(dev))
+        ns.append(g.n)
+        ms.append(g.m)
+    torch.cuda.synchronize()
+    print(f"[bench] c4: {count} graphs, sum n={sum(ns)} sum m={sum(ms)}, generated+uploaded in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    order = sorted(range(count), key=lambda i: -ms[i])       # largest first
+    o_csrs = [csrs[i] for i in order]
+    o_accs = [accs[i] for i in order]
+    o_ns = [ns[i] for i in order]
+    o_ms = [ms[i] for i in order]
+
+    def make(gang):
+        return mc.Batch(o_csrs, o_accs, gang=gang, device=dev)
+
+    per_gang, timings = autotune.tune(make, o_ns, o_ms, torch.cuda.get_device_name(0), use_cache=False,
+                                      log=lambda x: print(x, file=sys.stderr, flush=True))
+    gang = autotune.gang_sizes(o_ms, per_gang)
+    b = make(gang)
+    for _ in range(args.warmup):
+        b.launch()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        b.launch()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t) / args.steps
+    res_b = b.read()
+
+    # plain per-graph loop: one map_detect launch per graph, same order
+    res_one = mc.new_result(dev)
+    wsp = mc.workspace(max(ns), max(ms), device=dev)
+    plain = []
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    results_plain = torch.zeros((count, 8), dtype=torch.int32, device=dev)
+    for j, c in enumerate(o_csrs):
+        rc = mc.map_detect(c.n, c.row_ptr, c.col, None, None, o_accs[j], results_plain[j], None, None, 0,
+                           mc.MAP_FLAG_NO_TRACE_DIGEST, wsp)
+        if rc:
+            raise mc.MapError(rc, "map_detect")
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t
+    plain = [mc.Result.from_tensor(results_plain[j]) for j in range(count)]
+
+    # the one-workgroup-per-graph launch captured in a HIP graph, replayed
+    t_graph = None
+    graph_ok = None
+    bg = make(None)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        bg.launch(stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    cg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(cg):
+        bg.launch()
+    graph_ok = True
+    reps = max(1, args.steps)
+    for r in range(reps):
+        bg.results.zero_()           # eager work between replays
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        cg.replay()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        t_graph = dt if t_graph is None else min(t_graph, dt)
+        graph_ok &= [x.verdict for x in bg.read()] == [x.verdict for x in res_b]
+
+    exact_vs_plain = all(x.verdict == y.verdict and x.accepting_left == y.accepting_left and x.status == 0
+                         and y.status == 0 for x, y in zip(res_b, plain))
+    gold_path = os.path.join(ROOT, "tests", "golden", "batch_c4.json")
+    exact_vs_oracle = None
+    if os.path.exists(gold_path) and count == 4096:
+        gold = json.load(open(gold_path))["verdicts"]
+        exact_vs_oracle = all([r.found, r.witness, r.iterations, r.accepting_left] == gold[i]
+                              for r, i in zip(res_b, order))
+    work = sum(r.iterations * m for r, m in zip(res_b, o_ms))
+    out = {
+        "metric": METRIC, "value": round(count / t_batch, 2), "unit": "graphs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_batch * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": WORKLOADS["c4"][0], "key": "c4", "graphs": count, "sum_n": int(sum(ns)),
+                   "sum_m": int(sum(ms)), "parallelism": "single GPU", "order": "largest first",
+                   "per_gang": per_gang},
+        "plain_graphs_per_s": round(count / t_plain, 2), "plain_ms": round(t_plain * 1e3, 3),
+        "speedup_vs_plain": round(t_plain / t_batch, 3),
+        "hipgraph_graphs_per_s": round(count / t_graph, 2) if t_graph else None,
+        "hipgraph_replays_identical": graph_ok,
+        "gteps_batch": round(work / t_batch / 1e9, 4),
+        "tuner_ms": {k: round(v * 1e3, 3) for k, v in timings.items()},
+        "exact_vs_plain": exact_vs_plain, "exact_vs_oracle_golden": exact_vs_oracle,
+        "found": int(sum(r.found for r in res_b)),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Serving: Poisson arrivals at rho x the serial plain throughput; p50/p99 and graphs/s."""
+    import torch
+    from paper_0912_2555_amd import autotune, serve
+    import synth
+
+    torch.cuda.set_device(0)
+    count = args.serve_count
+    t0 = time.perf_counter()
+    graphs = [synth.config5(i) for i in range(count)]
+    gaps = [synth.config5_meta(i)[2] for i in range(count)]
+    print(f"[bench] c5: {count} queries, sum n={sum(g.n for g in graphs)}, generated in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    def queries():
+        return [serve.Query(i, g.n, g.src, g.dst, g.acc) for i, g in enumerate(graphs)]
+
+    # serial plain throughput, saturated (back-to-back), on a sample
+    sample = queries()[:min(count, 64)]
+    serve.run_serial(sample[:4], qps=1e9)                      # warm-up
+    sat, _ = serve.run_serial(sample, qps=1e9)
+    rate = sat["graphs_per_s"]
+    qps = args.rho * rate
+    print(f"[bench] serial saturated {rate:.2f} graphs/s -> offered load {qps:.2f} queries/s", file=sys.stderr,
+          flush=True)
+    qs = queries()
+    srv = serve.Server(hbm_budget=32 << 30, max_inflight=2,
+                       gang_policy=lambda ms: autotune.gang_sizes(ms, args.serve_per_gang)
+                       if args.serve_per_gang else None)
+    st = serve.run_stream(qs, qps=qps, server=srv, gaps=gaps)
+    ser, ser_res = serve.run_serial(queries(), qps=qps, gaps=gaps)
+    exact = all(q.result.status == 0 and q.result.verdict == r.verdict and q.result.accepting_left == r.accepting_left
+                for q, r in zip(qs, ser_res))
+    out = {
+        "metric": METRIC, "value": round(st["graphs_per_s"], 3), "unit": "graphs/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": round(st["span_s"] * 1e3, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": WORKLOADS["c5"][0], "key": "c5", "queries": count, "rho": args.rho,
+                   "offered_qps": round(qps, 3), "hbm_budget_gib": 32, "max_inflight": 2,
+                   "per_gang": args.serve_per_gang, "parallelism": "single GPU"},
+        "serving": {k: round(v, 3) if isinstance(v, float) else v for k, v in st.items()},
+        "serial_plain": {k: round(v, 3) for k, v in ser.items()},
+        "serial_saturated_graphs_per_s": round(rate, 3),
+        "exact_vs_serial": exact,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def calibrate_copy(args):
+    """A plain device copy of known size, for scaling the HBM traffic counters."""
+    import torch
+    nbytes = args.copy_mib << 20
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "device copy", "bytes_read": nbytes, "bytes_written": nbytes, "launches": 3}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,11 +276,27 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--sync-sweeps", action="store_true", help="grid barrier after every sweep")
     ap.add_argument("--stream", action="store_true", help="stream the CSR every sweep (no on-chip staging)")
+    ap.add_argument("--batch-count", type=int, default=4096, help="graphs in the config-4 batch")
+    ap.add_argument("--calibrate-copy", action="store_true", help="run a plain copy of known size and exit")
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--serve-count", type=int, default=1000, help="queries in the config-5 stream")
+    ap.add_argument("--rho", type=float, default=0.9, help="offered load / serial saturated throughput")
+    ap.add_argument("--serve-per-gang", type=int, default=1 << 18, help="edges per workgroup when serving (0: one)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(graphs shard by vertex range across GPUs only in the design notes)", file=sys.stderr)
         sys.exit(2)
+
+    if args.calibrate_copy:
+        calibrate_copy(args)
+        return
+    if args.workload == "c4":
+        bench_batch(args)
+        return
+    if args.workload == "c5":
+        bench_serve(args)
+        return
 
     import torch
     import paper_0912_2555_amd as mc

@@ -138,6 +138,38 @@ int map_detect(int32_t n, const int32_t *row_ptr, const int32_t *col, const int3
                int32_t trace_cap, uint8_t *accepting_out, int32_t max_iterations, uint32_t flags, void *ws,
                size_t ws_bytes, void *stream);
 
+/* One graph of a batch (device memory; see map_detect_batch). */
+typedef struct map_graph_desc {
+  int32_t n;                  /* vertices, ids 1..n */
+  int32_t reserved;           /* 0 */
+  int64_t m;                  /* edges */
+  const int32_t *row_ptr;     /* device pull CSR from map_build_csr: int32[n+1] */
+  const int32_t *col;         /* device int32[m] */
+  const uint8_t *accepting0;  /* device uint8[n]: A_1, not modified */
+} map_graph_desc;
+
+/*
+ * Bytes of device workspace for map_detect_batch over `count` graphs whose
+ * vertex counts sum to total_n (host only; 0 when out of range).
+ */
+size_t map_batch_workspace_bytes(int32_t count, int64_t total_n, uint32_t flags);
+
+/*
+ * The MAP outer loop (as map_detect) for many independent graphs in one
+ * persistent launch: a device work queue hands each graph to a gang of
+ * gang[g] workgroups (1..64; NULL = 1 for every graph), in the order given
+ * (put the largest graphs first).  With gang == NULL no workgroup ever waits
+ * on another, so the launch is an ordinary one and can be captured in a HIP
+ * graph; otherwise it is a cooperative launch.
+ *   graphs   device map_graph_desc[count].
+ *   gang     device int32[count] or NULL.
+ *   results  device map_result[count] out (as map_detect, one per graph).
+ *   total_n  sum of graphs[g].n (sizes the scratch; checked on the device,
+ *            every result gets MAP_ENOSPC if it does not fit).
+ */
+int map_detect_batch(int32_t count, const map_graph_desc *graphs, const int32_t *gang, map_result *results,
+                     int64_t total_n, uint32_t flags, void *ws, size_t ws_bytes, void *stream);
+
 /* Static description of a status code. */
 const char *map_strerror(int status);
 

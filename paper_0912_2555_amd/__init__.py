@@ -43,7 +43,8 @@ MAP_FLAG_NO_TRACE_DIGEST = 0x2
 MAP_FLAG_STREAM = 0x4
 MAP_FLAG_SYNC_SWEEPS = 0x8
 
-EXPORTS = ("map_workspace_bytes", "map_build_csr", "map_propagate", "map_detect", "map_strerror")
+EXPORTS = ("map_workspace_bytes", "map_build_csr", "map_propagate", "map_detect", "map_batch_workspace_bytes",
+           "map_detect_batch", "map_strerror")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_0912_2555_amd.build` "
@@ -59,6 +60,10 @@ _lib.map_propagate.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u32, _v
 _lib.map_propagate.restype = ctypes.c_int
 _lib.map_detect.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _i32, _u32, _vp, _sz, _vp]
 _lib.map_detect.restype = ctypes.c_int
+_lib.map_batch_workspace_bytes.argtypes = [_i32, _i64, _u32]
+_lib.map_batch_workspace_bytes.restype = _sz
+_lib.map_detect_batch.argtypes = [_i32, _vp, _vp, _vp, _i64, _u32, _vp, _sz, _vp]
+_lib.map_detect_batch.restype = ctypes.c_int
 _lib.map_strerror.argtypes = [ctypes.c_int]
 _lib.map_strerror.restype = ctypes.c_char_p
 
@@ -120,6 +125,15 @@ def map_detect(n, row_ptr, col, rrow_ptr, rcol, accepting0, result, trace, accep
     return _lib.map_detect(n, _ptr(row_ptr), _ptr(col), _ptr(rrow_ptr), _ptr(rcol), _ptr(accepting0),
                            _ptr(result), _ptr(trace), cap, _ptr(accepting_out), max_iterations, flags, _ptr(ws),
                            0 if ws is None else ws.numel() * ws.element_size(), _stream(stream))
+
+
+def map_batch_workspace_bytes(count: int, total_n: int, flags: int = 0) -> int:
+    return int(_lib.map_batch_workspace_bytes(count, total_n, flags))
+
+
+def map_detect_batch(count, graphs, gang, results, total_n, flags, ws, stream=None) -> int:
+    return _lib.map_detect_batch(count, _ptr(graphs), _ptr(gang), _ptr(results), total_n, flags, _ptr(ws),
+                                 0 if ws is None else ws.numel() * ws.element_size(), _stream(stream))
 
 
 # ---------------------------------------------------------------- wrappers
@@ -222,3 +236,42 @@ def detect(csr: Csr, accepting0, trace_cap: int = 0, want_acc: bool = False, max
     if trace is not None:
         tr = trace.cpu().numpy().view(np.uint64)[:min(r.iterations, trace_cap)].copy()
     return DetectOut(r, tr, acc_out.cpu().numpy() if acc_out is not None else None)
+
+
+# ------------------------------------------------------------------ batches
+
+GRAPH_DESC = np.dtype([("n", "<i4"), ("reserved", "<i4"), ("m", "<i8"), ("row_ptr", "<u8"), ("col", "<u8"),
+                       ("accepting0", "<u8")])
+assert GRAPH_DESC.itemsize == 40
+
+
+class Batch:
+    """Device descriptors, results and workspace for map_detect_batch.
+
+    ``csrs`` and ``accs`` stay referenced so the device buffers outlive the
+    launch.  Graphs are processed in the order given.
+    """
+
+    def __init__(self, csrs, accs, gang=None, flags: int = 0, device="cuda"):
+        self.csrs = list(csrs)
+        self.accs = [torch.as_tensor(a, dtype=torch.uint8).to(device).contiguous() for a in accs]
+        self.count = len(self.csrs)
+        desc = np.zeros(self.count, GRAPH_DESC)
+        for i, (c, a) in enumerate(zip(self.csrs, self.accs)):
+            desc[i] = (c.n, 0, c.m, c.row_ptr.data_ptr(), c.col.data_ptr(), a.data_ptr())
+        self.desc = torch.from_numpy(desc.view(np.uint8).copy()).to(device)
+        self.gang = None if gang is None else torch.as_tensor(np.asarray(gang, np.int32)).to(device)
+        self.total_n = int(sum(c.n for c in self.csrs))
+        self.results = torch.zeros((self.count, 8), dtype=torch.int32, device=device)
+        nbytes = map_batch_workspace_bytes(self.count, self.total_n, flags)
+        if nbytes == 0:
+            raise MapError(MAP_ERANGE, "map_batch_workspace_bytes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.flags = flags
+
+    def launch(self, stream=None):
+        _check(map_detect_batch(self.count, self.desc, self.gang, self.results, self.total_n, self.flags, self.ws,
+                                stream), "map_detect_batch")
+
+    def read(self):
+        return [Result.from_tensor(self.results[i]) for i in range(self.count)]

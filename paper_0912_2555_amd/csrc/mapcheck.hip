@@ -41,6 +41,7 @@ constexpr int kResRowsPerLane = 4;                     // resident mode: rows pe
 constexpr int kResWaveRows = kWave * kResRowsPerLane;  // resident mode: rows per wave
 constexpr int kResEdges = 24576;                        // resident mode: CSR edges per block in LDS
 constexpr int kGatherBatch = 12;                        // resident mode: gathers in flight per lane
+constexpr int kLocalPasses = 2;                         // resident mode: LDS-only passes after a sweep
 constexpr int kSortSlots = 1024;                        // resident mode: bitonic sort width (>= 64 * kGatherBatch)
 constexpr int kSortPerLane = kSortSlots / kWave;
 static_assert(kSortSlots >= kWave * kGatherBatch, "sort must cover a gather batch");
@@ -51,6 +52,7 @@ constexpr int kStripes = 16;
 constexpr int kSets = 3;
 constexpr int kMaxGroups = 8;  // barrier arrival groups (one per XCD)
 constexpr int kMaxBlocks = 2048;  // upper bound on the loop kernel's grid
+constexpr int kMaxGang = 64;      // upper bound on the blocks that share one graph of a batch
 // Bound on one barrier wait, in ticks of the 100 MHz device wall clock (10 s):
 // far beyond any legitimate phase, so a broken launch exits instead of hanging.
 constexpr uint64_t kWaitTicks = 1000000000ull;
@@ -70,7 +72,11 @@ struct alignas(128) Line64 {
   unsigned long long pad[15];
 };
 
-struct Ctrl {
+// Control block of one set of cooperating blocks: the whole grid for a single
+// graph, or the gang of blocks that solves one graph of a batch.  Q bounds the
+// number of blocks in the set.
+template <int Q>
+struct CtrlT {
   Line64 grp[kMaxGroups];  // barrier arrivals per group: high 32 = arrivals, low 32 = payload sum
   Line64 top;              // arrivals of the group leaders
   alignas(128) uint32_t gen;       // barrier generation
@@ -84,10 +90,13 @@ struct Ctrl {
   uint32_t pad1[31];
   alignas(128) uint32_t done;
   uint32_t pad2[31];
-  unsigned long long quiet[kMaxBlocks];
+  unsigned long long quiet[Q];
 };
+using Ctrl = CtrlT<kMaxBlocks>;
+using GangCtrl = CtrlT<kMaxGang>;
 constexpr size_t kCtrlBytes = 32768;
 static_assert(sizeof(Ctrl) <= kCtrlBytes, "ctrl block too large");
+constexpr size_t kGangCtrlBytes = (sizeof(GangCtrl) + 255) & ~(size_t)255;
 
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -130,13 +139,15 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
 
 // ------------------------------------------------------------ grid barrier --
 
+template <typename C>
 struct Grid {
-  Ctrl* c;
+  C* c;
   uint32_t gen;      // generation this block expects to complete next
   int nblocks;
   int group;         // arrival group of this block
   int group_size;    // blocks in this group
   int ngroups;
+  int rank;          // index of this block in the set
 };
 
 // Grid-wide barrier with a summed 32-bit payload.  Every thread must call it.
@@ -147,13 +158,29 @@ struct Grid {
 // barrier); the last arrival of a group and the last group leader acquire
 // before forwarding; waiters poll with relaxed loads (no cache invalidation
 // per poll) and acquire once when the generation moves.
-__device__ bool grid_sync(Grid& g, uint32_t payload, uint32_t* total) {
+template <typename C>
+__device__ bool grid_sync(Grid<C>& g, uint32_t payload, uint32_t* total) {
   __shared__ uint32_t s_total;
   __shared__ int s_ok;
+  if (g.nblocks == 1) {
+    // A single block: a workgroup barrier orders everything it shares.
+    __syncthreads();
+    if (threadIdx.x < kStripes) {
+      Stripe& s = g.c->sets[(g.gen + 2) % kSets][threadIdx.x];
+      __hip_atomic_store(&s.digest, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      st_agent(&s.count, 0u);
+      __hip_atomic_store(&s.witness, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      st_agent(&s.nonzero, 0u);
+    }
+    __syncthreads();
+    g.gen++;
+    if (total) *total = payload;
+    return true;
+  }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __syncthreads();
   if (threadIdx.x == 0) {
-    Ctrl* c = g.c;
+    C* c = g.c;
     int ok = 1;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const unsigned long long inc = (1ull << 32) | payload;
@@ -189,7 +216,7 @@ __device__ bool grid_sync(Grid& g, uint32_t payload, uint32_t* total) {
   __syncthreads();
   // Epoch E+1 writes set (E+1)%3 and reads set E%3; set (E-1)%3 was last read
   // during epoch E, so block 0 clears it now for epoch E+2.
-  if (blockIdx.x == 0 && threadIdx.x < kStripes) {
+  if (g.rank == 0 && threadIdx.x < kStripes) {
     Stripe& s = g.c->sets[(g.gen + 2) % kSets][threadIdx.x];
     __hip_atomic_store(&s.digest, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     st_agent(&s.count, 0u);
@@ -244,6 +271,7 @@ struct ResLds {
   int32_t col[kResEdges];
   uint8_t roff[kResEdges];
   uint32_t best[kWavesPerBlock][kResWaveRows];
+  uint32_t pv[kWavesPerBlock * kResWaveRows];  // the block's own packed values (row - block base)
 };
 
 union BlockLds {
@@ -252,6 +280,7 @@ union BlockLds {
 };
 
 struct WaveRows {
+  int64_t rb0, rb1;  // rows of this block
   int64_t r0, r1;  // rows of this wave
   int32_t we0, we1;  // resident: edge range of the wave inside the block's LDS slice
   bool resident;
@@ -345,10 +374,16 @@ __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int64_t r0
 }
 
 // Resident mode: one sweep over the wave's rows from its LDS slice.
-template <bool kFirst>
+// kFirst: the reset sweep (successors send their id if accepting).
+// kLocal: a pass over edges whose target is a row of this block only, reading
+// the block's values from LDS (values move along in-block edges without a
+// round trip to memory).  Otherwise in-block targets are read from LDS and the
+// others gathered from memory.
+template <bool kFirst, bool kLocal>
 __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, WaveRows& W, ResLds& R, int wib,
                                    int lane, uint32_t* acc_count) {
   uint32_t* best = R.best[wib];
+  const uint32_t base = (uint32_t)W.rb0, span = (uint32_t)(W.rb1 - W.rb0);
 #pragma unroll
   for (int j = 0; j < kResRowsPerLane; ++j) best[lane + j * kWave] = 0;
   wave_lds_sync();
@@ -363,7 +398,12 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, WaveRo
 #pragma unroll
     for (int u = 0; u < kGatherBatch; ++u) {
       x[u] = 0;
-      if ((uint32_t)w[u] < (uint32_t)a.n) x[u] = kFirst ? sent_first(acc, w[u]) : sent_packed(a.pv[w[u]], w[u]);
+      if ((uint32_t)w[u] < (uint32_t)a.n) {
+        const uint32_t local = (uint32_t)w[u] - base;
+        if (kFirst) x[u] = sent_first(acc, w[u]);
+        else if (local < span) x[u] = sent_packed(R.pv[local], w[u]);
+        else if (!kLocal) x[u] = sent_packed(a.pv[w[u]], w[u]);
+      }
     }
 #pragma unroll
     for (int u = 0; u < kGatherBatch; ++u) {
@@ -383,10 +423,12 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, WaveRo
         nacc += isacc;
         W.own[j] = (isacc << 31) | b;
         a.pv[v] = W.own[j];
+        R.pv[v - W.rb0] = W.own[j];
         changed |= b != 0;
       } else if (b > (W.own[j] & kValMask)) {
         W.own[j] = (W.own[j] & kAccBit) | b;
         a.pv[v] = W.own[j];
+        R.pv[v - W.rb0] = W.own[j];
         changed = 1;
       }
     }
@@ -395,10 +437,28 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, WaveRo
   return __ballot(changed) != 0;
 }
 
+// One sweep of the block's rows.  Every thread of the block calls it.  In
+// resident mode up to kLocalPasses LDS-only passes over in-block edges follow
+// the sweep (they stop early once a pass changes nothing in the block).
 template <bool kFirst>
 __device__ uint32_t sweep_rows(const LoopArgs& a, const uint8_t* acc, WaveRows& W, BlockLds& S, int wib, int lane,
                                uint32_t* acc_count) {
-  if (W.resident) return sweep_resident<kFirst>(a, acc, W, S.res, wib, lane, acc_count);
+  __shared__ uint32_t s_any;
+  if (W.resident) {
+    uint32_t ch = sweep_resident<kFirst, false>(a, acc, W, S.res, wib, lane, acc_count);
+    for (int p = 0; p < kLocalPasses; ++p) {
+      if (threadIdx.x == 0) s_any = 0;
+      __syncthreads();  // the block's LDS values of the previous pass are complete
+      const uint32_t lc = sweep_resident<false, true>(a, acc, W, S.res, wib, lane, nullptr);
+      if (lc && lane == 0) atomicOr(&s_any, 1u);
+      ch |= lc;
+      __syncthreads();
+      const uint32_t any = s_any;
+      __syncthreads();
+      if (!any) break;
+    }
+    return ch;
+  }
   uint32_t ch = 0;
   if (W.r1 > W.r0) {
     // Tiles in decreasing row order: values mostly flow from high ids to low.
@@ -476,7 +536,11 @@ __device__ void sort_gather_batches(ResLds& R, int32_t we0, int32_t we1, int lan
   }
 }
 
-__global__ void __launch_bounds__(kBlock) map_loop_kernel(LoopArgs a) {
+// The whole MAP computation for one graph, run by `nb` cooperating blocks of
+// which this is block `b`; `logical` is the block's position in row order.
+// Every block of the set must call it; c is the set's zeroed control block.
+template <typename C>
+__device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, const int logical) {
   __shared__ BlockLds S;
   __shared__ uint32_t s_red[kWavesPerBlock];
   __shared__ unsigned long long s_red64[kWavesPerBlock];
@@ -484,11 +548,6 @@ __global__ void __launch_bounds__(kBlock) map_loop_kernel(LoopArgs a) {
 
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = threadIdx.x / kWave;
-  const int nb = gridDim.x;
-  const int b = blockIdx.x;
-  // XCD-aware numbering: consecutive hardware block ids land on different
-  // XCDs; give each XCD a contiguous range of logical blocks (and rows).
-  const int logical = (nb % kMaxGroups == 0) ? (b % kMaxGroups) * (nb / kMaxGroups) + b / kMaxGroups : b;
 
   // Row ranges of this block and wave.
   const int64_t rows_per_block = ((int64_t)a.n + nb - 1) / nb;
@@ -496,6 +555,8 @@ __global__ void __launch_bounds__(kBlock) map_loop_kernel(LoopArgs a) {
   const int64_t rb1 = min((int64_t)a.n, rb0 + rows_per_block);
   const int64_t rows_per_wave = (rows_per_block + kWavesPerBlock - 1) / kWavesPerBlock;
   WaveRows W;
+  W.rb0 = rb0;
+  W.rb1 = rb1;
   W.r0 = min(rb1, rb0 + (int64_t)wib * rows_per_wave);
   W.r1 = min(rb1, W.r0 + rows_per_wave);
   W.we0 = W.we1 = 0;
@@ -523,15 +584,14 @@ __global__ void __launch_bounds__(kBlock) map_loop_kernel(LoopArgs a) {
     }
   }
 
-  Grid g;
-  g.c = a.ctrl;
+  Grid<C> g;
+  g.c = c;
   g.gen = 0;
   g.nblocks = nb;
   g.ngroups = min(nb, kMaxGroups);
   g.group = b % g.ngroups;
   g.group_size = nb / g.ngroups + ((b % g.ngroups) < (nb % g.ngroups) ? 1 : 0);
-
-  Ctrl* c = a.ctrl;
+  g.rank = b;
   uint8_t* acc = a.propagate ? const_cast<uint8_t*>(a.acc_in) : a.accw;
 
   // Block-level sum of per-wave u32 values followed by one striped atomic.
@@ -607,7 +667,7 @@ __global__ void __launch_bounds__(kBlock) map_loop_kernel(LoopArgs a) {
     }
     k++;
     int64_t s = 1;
-    if (a.sync_sweeps) {
+    if (a.sync_sweeps || nb == 1) {
       while (tot != 0) {
         if (s > (int64_t)a.n + 1) { status = MAP_ENOTCONVERGED; break; }
         uint32_t c2 = sweep_rows<false>(a, acc, W, S, wib, lane, nullptr);
@@ -761,6 +821,142 @@ done:
 aborted:
   if (threadIdx.x == 0) {
     __hip_atomic_store(&a.result->status, (int32_t)MAP_EDEVICE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kBlock) map_loop_kernel(LoopArgs a) {
+  const int nb = gridDim.x;
+  const int b = blockIdx.x;
+  // XCD-aware numbering: consecutive hardware block ids land on different
+  // XCDs; give each XCD a contiguous range of logical blocks (and rows).
+  const int logical = (nb % kMaxGroups == 0) ? (b % kMaxGroups) * (nb / kMaxGroups) + b / kMaxGroups : b;
+  map_body<Ctrl>(a, a.ctrl, nb, b, logical);
+}
+
+// ------------------------------------------------------------------ batch --
+
+struct BatchArgs {
+  int32_t count;
+  const map_graph_desc* graphs;
+  map_result* results;
+  const int32_t* item_start;  // [count + 1]: first work item of each graph
+  const int64_t* scratch_off;  // [count]: byte offset of each graph's scratch
+  GangCtrl* gctrl;             // [count]
+  char* scratch;
+  uint32_t* next_item;
+  int32_t* status;             // MAP_ENOSPC when the scratch does not fit
+  uint32_t flags;
+};
+
+// One graph of a batch, out of line so that its register allocation is not
+// shared with the work-queue loop around it.
+__device__ __noinline__ void map_body_gang(const LoopArgs& a, GangCtrl* c, int nb, int rank) {
+  map_body<GangCtrl>(a, c, nb, rank, rank);
+}
+
+// Persistent work queue over the graphs of a batch.  Graph g is solved by
+// item_start[g+1] - item_start[g] blocks (its gang); each block pops one item
+// (graph, rank) at a time.  Items of a gang are consecutive in the queue, so a
+// gang is always completed by blocks that free up, and it never waits on a
+// later one.
+__global__ void __launch_bounds__(kBlock) map_batch_kernel(BatchArgs ba) {
+  __shared__ int32_t s_item;
+  const int32_t total = ba.item_start[ba.count];
+  if (__hip_atomic_load(ba.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != MAP_OK) {
+    for (int32_t gi = blockIdx.x * blockDim.x + threadIdx.x; gi < ba.count; gi += gridDim.x * blockDim.x)
+      ba.results[gi].status = MAP_ENOSPC;
+    return;
+  }
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int32_t)__hip_atomic_fetch_add(ba.next_item, 1u, __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int32_t item = s_item;
+    __syncthreads();
+    if (item >= total) break;
+    int32_t lo = 0, hi = ba.count;  // largest gi with item_start[gi] <= item
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (ba.item_start[mid] <= item) lo = mid; else hi = mid;
+    }
+    const int32_t gi = lo;
+    const int nb = ba.item_start[gi + 1] - ba.item_start[gi];
+    const int rank = item - ba.item_start[gi];
+    const map_graph_desc d = ba.graphs[gi];
+    if (d.n < 1 || d.n > 0x7ffffffe || !d.row_ptr || !d.col || !d.accepting0) {
+      if (rank == 0 && threadIdx.x == 0) {
+        ba.results[gi].status = MAP_EINVAL;
+        ba.results[gi].found = ba.results[gi].witness = ba.results[gi].iterations = 0;
+      }
+      continue;
+    }
+    char* base = ba.scratch + ba.scratch_off[gi];
+    LoopArgs a;
+    a.n = d.n;
+    a.ntiles = (int32_t)(((int64_t)d.n + kTileRows - 1) / kTileRows);
+    a.row_ptr = d.row_ptr;
+    a.col = d.col;
+    a.acc_in = d.accepting0;
+    a.pv = reinterpret_cast<uint32_t*>(base);
+    a.accw = reinterpret_cast<uint8_t*>(base + (((size_t)d.n * 4 + 255) & ~(size_t)255));
+    a.ctrl = nullptr;
+    a.result = ba.results + gi;
+    a.trace = nullptr;
+    a.trace_cap = 0;
+    a.acc_out = nullptr;
+    a.map_out = nullptr;
+    a.max_iter = 0;
+    a.propagate = 0;
+    a.digest = 0;
+    a.force_stream = (ba.flags & MAP_FLAG_STREAM) ? 1 : 0;
+    a.sync_sweeps = (ba.flags & MAP_FLAG_SYNC_SWEEPS) ? 1 : 0;
+    map_body_gang(a, ba.gctrl + gi, nb, rank);
+  }
+}
+
+// Batch set-up (one block): gang sizes -> work item offsets, scratch offsets,
+// and the scratch size check.
+__global__ void __launch_bounds__(1024) batch_plan(int32_t count, const map_graph_desc* graphs,
+                                                   const int32_t* gang, int32_t* item_start, int64_t* scratch_off,
+                                                   size_t scratch_bytes, int32_t* status, uint32_t* next_item) {
+  __shared__ int64_t part_i[1024];
+  __shared__ int64_t part_b[1024];
+  const int64_t per = ((int64_t)count + 1023) / 1024;
+  const int64_t lo = (int64_t)threadIdx.x * per, hi = min((int64_t)count, lo + per);
+  int64_t si = 0, sb = 0;
+  for (int64_t i = lo; i < hi; ++i) {
+    int32_t gsz = gang ? gang[i] : 1;
+    gsz = max(1, min(gsz, kMaxGang));
+    si += gsz;
+    const int64_t n = max(graphs[i].n, 1);
+    sb += (int64_t)((n * 4 + 255) & ~255) + (int64_t)((n + 255) & ~255);
+  }
+  part_i[threadIdx.x] = si;
+  part_b[threadIdx.x] = sb;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int64_t yi = threadIdx.x >= off ? part_i[threadIdx.x - off] : 0;
+    const int64_t yb = threadIdx.x >= off ? part_b[threadIdx.x - off] : 0;
+    __syncthreads();
+    part_i[threadIdx.x] += yi;
+    part_b[threadIdx.x] += yb;
+    __syncthreads();
+  }
+  int64_t pi = threadIdx.x ? part_i[threadIdx.x - 1] : 0;
+  int64_t pb = threadIdx.x ? part_b[threadIdx.x - 1] : 0;
+  for (int64_t i = lo; i < hi; ++i) {
+    item_start[i] = (int32_t)pi;
+    scratch_off[i] = pb;
+    int32_t gsz = gang ? gang[i] : 1;
+    pi += max(1, min(gsz, kMaxGang));
+    const int64_t n = max(graphs[i].n, 1);
+    pb += (int64_t)((n * 4 + 255) & ~255) + (int64_t)((n + 255) & ~255);
+  }
+  if (threadIdx.x == 1023) {
+    item_start[count] = (int32_t)part_i[1023];
+    *status = (size_t)part_b[1023] <= scratch_bytes ? MAP_OK : MAP_ENOSPC;
+    *next_item = 0;
   }
 }
 
@@ -978,6 +1174,48 @@ int build_one(int32_t n, int64_t m, const int32_t* key, const int32_t* other, in
   return hipGetLastError() == hipSuccess ? MAP_OK : MAP_EDEVICE;
 }
 
+struct BatchLayout {
+  size_t header, item_start, scratch_off, gctrl, scratch, total;
+};
+
+BatchLayout batch_layout(int32_t count, int64_t total_n) {
+  BatchLayout L;
+  size_t off = 0;
+  L.header = off;
+  off += 256;
+  L.item_start = off;
+  off += align256(((size_t)count + 1) * 4);
+  L.scratch_off = off;
+  off += align256((size_t)count * 8);
+  L.gctrl = off;
+  off += (size_t)count * kGangCtrlBytes;
+  L.scratch = off;
+  off += (size_t)total_n * 5 + (size_t)count * 512;
+  L.total = off;
+  return L;
+}
+
+int batch_device_info(int* cus, int* per_cu) {
+  static std::mutex mu;
+  static int cache_cus[64], cache_per[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return MAP_EDEVICE;
+  std::lock_guard<std::mutex> lock(mu);
+  if (cache_cus[dev] == 0) {
+    int c = 0, nb = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return MAP_EDEVICE;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(map_batch_kernel), kBlock,
+                                                     0) != hipSuccess)
+      return MAP_EDEVICE;
+    if (c <= 0 || nb <= 0) return MAP_EDEVICE;
+    cache_cus[dev] = c;
+    cache_per[dev] = nb;
+  }
+  *cus = cache_cus[dev];
+  *per_cu = cache_per[dev];
+  return MAP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1060,6 +1298,55 @@ int map_detect(int32_t n, const int32_t* row_ptr, const int32_t* col, const int3
   a.force_stream = (flags & MAP_FLAG_STREAM) ? 1 : 0;
   a.sync_sweeps = (flags & MAP_FLAG_SYNC_SWEEPS) ? 1 : 0;
   return launch_loop(a, reinterpret_cast<hipStream_t>(stream));
+}
+
+size_t map_batch_workspace_bytes(int32_t count, int64_t total_n, uint32_t flags) {
+  (void)flags;
+  if (count < 1 || count > (1 << 24) || total_n < count || total_n > ((int64_t)1 << 40)) return 0;
+  return batch_layout(count, total_n).total;
+}
+
+int map_detect_batch(int32_t count, const map_graph_desc* graphs, const int32_t* gang, map_result* results,
+                     int64_t total_n, uint32_t flags, void* ws, size_t ws_bytes, void* stream) {
+  if (count < 1 || count > (1 << 24) || total_n < count || total_n > ((int64_t)1 << 40)) return MAP_ERANGE;
+  if (!graphs || !results || !ws) return MAP_EINVAL;
+  if (flags & ~kAllFlags) return MAP_EINVAL;
+  const BatchLayout L = batch_layout(count, total_n);
+  if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return MAP_ENOSPC;
+  int cus = 0, per_cu = 0;
+  int rc = batch_device_info(&cus, &per_cu);
+  if (rc) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  BatchArgs ba;
+  ba.count = count;
+  ba.graphs = graphs;
+  ba.results = results;
+  ba.item_start = reinterpret_cast<int32_t*>(w + L.item_start);
+  ba.scratch_off = reinterpret_cast<int64_t*>(w + L.scratch_off);
+  ba.gctrl = reinterpret_cast<GangCtrl*>(w + L.gctrl);
+  ba.scratch = w + L.scratch;
+  ba.next_item = reinterpret_cast<uint32_t*>(w + L.header);
+  ba.status = reinterpret_cast<int32_t*>(w + L.header + 128);
+  ba.flags = flags;
+  const int64_t ctrl_words = (int64_t)((size_t)count * kGangCtrlBytes / 4);
+  hipLaunchKernelGGL(fill_u32, dim3(grid_for(ctrl_words, 256)), dim3(256), 0, st,
+                     reinterpret_cast<uint32_t*>(ba.gctrl), ctrl_words, 0u);
+  hipLaunchKernelGGL(batch_plan, dim3(1), dim3(1024), 0, st, count, graphs, gang,
+                     const_cast<int32_t*>(ba.item_start), const_cast<int64_t*>(ba.scratch_off),
+                     (size_t)(L.total - L.scratch), ba.status, ba.next_item);
+  if (hipGetLastError() != hipSuccess) return MAP_EDEVICE;
+  const int grid = cus * per_cu;
+  if (gang == nullptr) {
+    hipLaunchKernelGGL(map_batch_kernel, dim3(grid), dim3(kBlock), 0, st, ba);
+    if (hipGetLastError() != hipSuccess) return MAP_EDEVICE;
+  } else {
+    void* args[] = {&ba};
+    if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(map_batch_kernel), dim3(grid), dim3(kBlock), args,
+                                   0, st) != hipSuccess)
+      return MAP_EDEVICE;
+  }
+  return MAP_OK;
 }
 
 const char* map_strerror(int status) {

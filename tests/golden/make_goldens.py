@@ -3,7 +3,7 @@
 Calls only the CPU oracle and the seeded generators; nothing here touches the
 HIP library.  Run from the repository root:
 
-    python tests/golden/make_goldens.py [config2|config3|all]
+    python tests/golden/make_goldens.py [config2|config3|config4|all]
 
 Each record holds the verdict (found, witness, K), the accepting count at
 exit, the per-iteration |Del_k| list and the per-iteration map digests
@@ -44,6 +44,21 @@ def record(g, label):
     }
 
 
+def batch_record(count=4096, seed=4):
+    """Verdicts of every graph of the config-4 batch: [found, witness, K, |A| at exit]."""
+    t = time.time()
+    rows, ns, ms = [], [], []
+    for i in range(count):
+        g = synth.config4(i, seed=seed)
+        d = oracle.map_detect(g, mode="desc")
+        rows.append([d.found, d.witness, d.iterations, d.accepting_left])
+        ns.append(g.n)
+        ms.append(g.m)
+    return {"label": f"config 4 batch ({count} graphs, seed {seed})", "count": count, "seed": seed,
+            "total_n": int(sum(ns)), "total_m": int(sum(ms)), "verdicts": rows,
+            "oracle_seconds": round(time.time() - t, 1)}
+
+
 def main(which):
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     if which in ("config2", "all"):
@@ -53,6 +68,11 @@ def main(which):
         data["c3"] = record(synth.config3(), "config 3 (2^25-vertex DAG, 0.1% accepting)")
     with open(OUT, "w") as f:
         json.dump(data, f, indent=1)
+    if which in ("config4", "all"):
+        rec = batch_record()
+        with open(os.path.join(ROOT, "tests", "golden", "batch_c4.json"), "w") as f:
+            json.dump(rec, f, separators=(",", ":"))
+        print("c4", rec["count"], rec["total_n"], rec["oracle_seconds"])
     for k, v in data.items():
         print(k, v["found"], v["witness"], v["iterations"], v["accepting_left"], v["oracle_seconds"])
 

@@ -37,7 +37,8 @@ def declared_functions():
 
 def test_exports_every_declared_symbol(lib):
     names = declared_functions()
-    assert names == ["map_build_csr", "map_detect", "map_propagate", "map_strerror", "map_workspace_bytes"]
+    assert names == ["map_batch_workspace_bytes", "map_build_csr", "map_detect", "map_detect_batch", "map_propagate",
+                     "map_strerror", "map_workspace_bytes"]
     for name in names:
         assert hasattr(lib, name), name
 
