@@ -47,6 +47,12 @@ constexpr int kSortPerLane = kSortSlots / kWave;
 static_assert(kSortSlots >= kWave * kGatherBatch, "sort must cover a gather batch");
 constexpr uint32_t kAllFlags = MAP_FLAG_DENSE_ONLY | MAP_FLAG_NO_TRACE_DIGEST | MAP_FLAG_STREAM | MAP_FLAG_SYNC_SWEEPS;
 constexpr uint32_t kAccBit = 0x80000000u;
+
+// Global-memory views of device pointers, for out-of-line functions where the
+// address space of a pointer loaded from an argument struct is not inferred.
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+typedef __attribute__((address_space(1))) const int32_t g_ci32;
+typedef __attribute__((address_space(1))) const uint8_t g_cu8;
 constexpr uint32_t kValMask = 0x7fffffffu;
 constexpr int kStripes = 16;
 constexpr int kSets = 3;
@@ -249,6 +255,8 @@ struct LoopArgs {
   int32_t digest;     // 1: compute the trace digest
   int32_t force_stream;  // 1: never stage the CSR in LDS
   int32_t sync_sweeps;   // 1: a grid barrier after every sweep instead of the asynchronous fixpoint
+  uint32_t val_mask;     // bits of a packed word holding the map value
+  uint32_t par_bit;      // bit holding the iteration parity (0: untagged, n >= 2^30)
 };
 
 // Row ownership: the rows are cut into one contiguous range per block and,
@@ -284,8 +292,13 @@ struct WaveRows {
   int64_t r0, r1;  // rows of this wave
   int32_t we0, we1;  // resident: edge range of the wave inside the block's LDS slice
   bool resident;
-  uint32_t own[kResRowsPerLane];  // resident: packed values of rows r0 + lane + 64 j
 };
+
+// The block's LDS, at namespace scope so that out-of-line sweep functions
+// address it directly (LDS instructions, not generic pointers).  In resident
+// mode g_lds.res.pv holds the block's own packed values, the only copy a wave
+// reads its rows from.
+__shared__ BlockLds g_lds;
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -294,16 +307,20 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Value that successor w (0-based) sends along an edge: its map value, or its
-// own id if it is accepting and larger.
-__device__ __forceinline__ uint32_t sent_packed(uint32_t x, int32_t w) {
-  uint32_t m = x & kValMask;
-  uint32_t id = (uint32_t)w + 1u;
+// own id if it is accepting and larger.  A word tagged with the other
+// iteration parity has not been reset in this iteration yet and sends 0, a
+// valid lower bound (its owner's reset sweep then counts as a change, so the
+// reader sweeps again once the true value is there).
+__device__ __forceinline__ uint32_t sent_word(uint32_t x, int32_t w, uint32_t cur, uint32_t vmask, uint32_t pbit) {
+  const uint32_t id = (uint32_t)w + 1u;
+  if ((x & pbit) != cur) return 0u;
+  const uint32_t m = x & vmask;
   return (x & kAccBit) ? (m > id ? m : id) : m;
 }
 
 // What successor w sends in the first sweep of an iteration (map = 0 everywhere).
 __device__ __forceinline__ uint32_t sent_first(const uint8_t* acc, int32_t w) {
-  return acc[w] ? (uint32_t)w + 1u : 0u;
+  return ((g_cu8*)acc)[w] ? (uint32_t)w + 1u : 0u;
 }
 
 // Stream mode, rows [r0, r1) with r1 - r0 <= kTileRows, processed by one wave.
@@ -312,9 +329,14 @@ __device__ __forceinline__ uint32_t sent_first(const uint8_t* acc, int32_t w) {
 // its value grows.  Returns nonzero (wave-uniform) if some row changed.
 template <bool kFirst>
 __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int64_t r0, int64_t r1, TileLds& L, int lane,
-                               uint32_t* acc_count) {
+                               uint32_t cur, uint32_t* acc_count) {
   const int nr = (int)(r1 - r0);
-  for (int i = lane; i <= nr; i += kWave) L.rp[i] = __builtin_nontemporal_load(a.row_ptr + r0 + i);
+  g_ci32* row_ptr = (g_ci32*)a.row_ptr;
+  g_ci32* colp = (g_ci32*)a.col;
+  g_u32* pv = (g_u32*)a.pv;
+  g_cu8* gacc = (g_cu8*)acc;
+  const uint32_t n = (uint32_t)a.n, vmask = a.val_mask, pbit = a.par_bit;
+  for (int i = lane; i <= nr; i += kWave) L.rp[i] = __builtin_nontemporal_load(row_ptr + r0 + i);
   wave_lds_sync();
   const int32_t e0 = L.rp[0], e1 = L.rp[nr];
   int32_t lo[kRowsPerLane], hi[kRowsPerLane];
@@ -325,7 +347,7 @@ __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int64_t r0
     lo[j] = r < nr ? L.rp[r] : 0;
     hi[j] = r < nr ? L.rp[r + 1] : 0;
     best[j] = 0;
-    old[j] = (!kFirst && r < nr) ? a.pv[r0 + r] : 0u;
+    old[j] = (!kFirst && r < nr) ? pv[r0 + r] : 0u;
   }
   for (int32_t c0 = e0; c0 < e1; c0 += kTileEdges) {
     const int cnt = (int)min((int64_t)kTileEdges, (int64_t)e1 - c0);
@@ -333,13 +355,13 @@ __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int64_t r0
 #pragma unroll
     for (int u = 0; u < kEdgesPerLane; ++u) {
       int i = lane + u * kWave;
-      w[u] = i < cnt ? __builtin_nontemporal_load(a.col + c0 + i) : -1;
+      w[u] = i < cnt ? __builtin_nontemporal_load(colp + c0 + i) : -1;
     }
 #pragma unroll
     for (int u = 0; u < kEdgesPerLane; ++u) {
       int i = lane + u * kWave;
       uint32_t x = 0;
-      if ((uint32_t)w[u] < (uint32_t)a.n) x = kFirst ? sent_first(acc, w[u]) : sent_packed(a.pv[w[u]], w[u]);
+      if ((uint32_t)w[u] < n) x = kFirst ? sent_first(acc, w[u]) : sent_word(pv[w[u]], w[u], cur, vmask, pbit);
       if (i < cnt) L.val[i] = x;
     }
     wave_lds_sync();
@@ -359,12 +381,12 @@ __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int64_t r0
     if (r < nr) {
       int64_t v = r0 + r;
       if (kFirst) {
-        uint32_t isacc = acc[v] ? 1u : 0u;
+        uint32_t isacc = gacc[v] ? 1u : 0u;
         nacc += isacc;
-        a.pv[v] = (isacc << 31) | best[j];
-        changed |= best[j] != 0;
-      } else if (best[j] > (old[j] & kValMask)) {
-        a.pv[v] = (old[j] & kAccBit) | best[j];
+        pv[v] = (isacc << 31) | cur | best[j];
+        changed |= (best[j] | isacc) != 0;
+      } else if (best[j] > (old[j] & vmask)) {
+        pv[v] = (old[j] & ~vmask) | best[j];
         changed = 1;
       }
     }
@@ -380,9 +402,13 @@ __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int64_t r0
 // round trip to memory).  Otherwise in-block targets are read from LDS and the
 // others gathered from memory.
 template <bool kFirst, bool kLocal>
-__device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, WaveRows& W, ResLds& R, int wib,
-                                   int lane, uint32_t* acc_count) {
+__device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, const WaveRows& W, int wib, int lane,
+                                   uint32_t cur, uint32_t* acc_count) {
+  ResLds& R = g_lds.res;
   uint32_t* best = R.best[wib];
+  g_u32* pv = (g_u32*)a.pv;
+  g_cu8* gacc = (g_cu8*)acc;
+  const uint32_t n = (uint32_t)a.n, vmask = a.val_mask, pbit = a.par_bit;
   const uint32_t base = (uint32_t)W.rb0, span = (uint32_t)(W.rb1 - W.rb0);
 #pragma unroll
   for (int j = 0; j < kResRowsPerLane; ++j) best[lane + j * kWave] = 0;
@@ -398,11 +424,11 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, WaveRo
 #pragma unroll
     for (int u = 0; u < kGatherBatch; ++u) {
       x[u] = 0;
-      if ((uint32_t)w[u] < (uint32_t)a.n) {
+      if ((uint32_t)w[u] < n) {
         const uint32_t local = (uint32_t)w[u] - base;
         if (kFirst) x[u] = sent_first(acc, w[u]);
-        else if (local < span) x[u] = sent_packed(R.pv[local], w[u]);
-        else if (!kLocal) x[u] = sent_packed(a.pv[w[u]], w[u]);
+        else if (local < span) x[u] = sent_word(R.pv[local], w[u], cur, vmask, pbit);
+        else if (!kLocal) x[u] = sent_word(pv[w[u]], w[u], cur, vmask, pbit);
       }
     }
 #pragma unroll
@@ -419,17 +445,20 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, WaveRo
     if (v < W.r1) {
       uint32_t b = best[lane + j * kWave];
       if (kFirst) {
-        uint32_t isacc = acc[v] ? 1u : 0u;
+        uint32_t isacc = gacc[v] ? 1u : 0u;
         nacc += isacc;
-        W.own[j] = (isacc << 31) | b;
-        a.pv[v] = W.own[j];
-        R.pv[v - W.rb0] = W.own[j];
-        changed |= b != 0;
-      } else if (b > (W.own[j] & kValMask)) {
-        W.own[j] = (W.own[j] & kAccBit) | b;
-        a.pv[v] = W.own[j];
-        R.pv[v - W.rb0] = W.own[j];
-        changed = 1;
+        const uint32_t x = (isacc << 31) | cur | b;
+        pv[v] = x;
+        R.pv[v - W.rb0] = x;
+        changed |= (b | isacc) != 0;
+      } else {
+        const uint32_t old = R.pv[v - W.rb0];
+        if (b > (old & vmask)) {
+          const uint32_t x = (old & ~vmask) | b;
+          pv[v] = x;
+          R.pv[v - W.rb0] = x;
+          changed = 1;
+        }
       }
     }
   }
@@ -441,15 +470,15 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, WaveRo
 // resident mode up to kLocalPasses LDS-only passes over in-block edges follow
 // the sweep (they stop early once a pass changes nothing in the block).
 template <bool kFirst>
-__device__ uint32_t sweep_rows(const LoopArgs& a, const uint8_t* acc, WaveRows& W, BlockLds& S, int wib, int lane,
-                               uint32_t* acc_count) {
+__device__ uint32_t sweep_rows(const LoopArgs& a, const uint8_t* acc, const WaveRows W, int wib, int lane,
+                               uint32_t cur, uint32_t* acc_count) {
   __shared__ uint32_t s_any;
   if (W.resident) {
-    uint32_t ch = sweep_resident<kFirst, false>(a, acc, W, S.res, wib, lane, acc_count);
+    uint32_t ch = sweep_resident<kFirst, false>(a, acc, W, wib, lane, cur, acc_count);
     for (int p = 0; p < kLocalPasses; ++p) {
       if (threadIdx.x == 0) s_any = 0;
       __syncthreads();  // the block's LDS values of the previous pass are complete
-      const uint32_t lc = sweep_resident<false, true>(a, acc, W, S.res, wib, lane, nullptr);
+      const uint32_t lc = sweep_resident<false, true>(a, acc, W, wib, lane, cur, nullptr);
       if (lc && lane == 0) atomicOr(&s_any, 1u);
       ch |= lc;
       __syncthreads();
@@ -463,7 +492,7 @@ __device__ uint32_t sweep_rows(const LoopArgs& a, const uint8_t* acc, WaveRows& 
   if (W.r1 > W.r0) {
     // Tiles in decreasing row order: values mostly flow from high ids to low.
     for (int64_t t0 = W.r0 + ((W.r1 - W.r0 - 1) / kTileRows) * kTileRows; t0 >= W.r0; t0 -= kTileRows)
-      ch |= sweep_tile<kFirst>(a, acc, t0, min(W.r1, t0 + kTileRows), S.tile[wib], lane, acc_count);
+      ch |= sweep_tile<kFirst>(a, acc, t0, min(W.r1, t0 + kTileRows), g_lds.tile[wib], lane, cur, acc_count);
   }
   return ch;
 }
@@ -475,7 +504,7 @@ __device__ __forceinline__ void for_own_rows(const LoopArgs& a, const WaveRows& 
 #pragma unroll
     for (int j = 0; j < kResRowsPerLane; ++j) {
       int64_t v = W.r0 + lane + j * kWave;
-      if (v < W.r1) f(v, W.own[j]);
+      if (v < W.r1) f(v, g_lds.res.pv[v - W.rb0]);
     }
   } else {
     for (int64_t v = W.r0 + lane; v < W.r1; v += kWave) f(v, a.pv[v]);
@@ -487,7 +516,8 @@ __device__ __forceinline__ void for_own_rows(const LoopArgs& a, const WaveRows& 
 // instruction read neighbouring addresses and touch few cache lines.  Bitonic
 // network over kSortSlots keys held kSortSlots / 64 per lane (element i lives
 // in lane i % 64, slot i / 64); padding keys are 0xffffffff and sort last.
-__device__ void sort_gather_batches(ResLds& R, int32_t we0, int32_t we1, int lane) {
+__device__ void sort_gather_batches(int32_t we0, int32_t we1, int lane) {
+  ResLds& R = g_lds.res;
   for (int32_t k0 = we0; k0 < we1; k0 += kWave * kGatherBatch) {
     const int cnt = (int)min((int32_t)(kWave * kGatherBatch), we1 - k0);
     uint32_t key[kSortPerLane];
@@ -539,9 +569,12 @@ __device__ void sort_gather_batches(ResLds& R, int32_t we0, int32_t we1, int lan
 // The whole MAP computation for one graph, run by `nb` cooperating blocks of
 // which this is block `b`; `logical` is the block's position in row order.
 // Every block of the set must call it; c is the set's zeroed control block.
-template <typename C>
+// kAsync selects the fixpoint control at compile time: asynchronous sweeps with
+// quiescence detection, or a grid barrier after every sweep (required for a
+// single block, for untagged values, and with MAP_FLAG_SYNC_SWEEPS).
+template <typename C, bool kAsync>
 __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, const int logical) {
-  __shared__ BlockLds S;
+  BlockLds& S = g_lds;
   __shared__ uint32_t s_red[kWavesPerBlock];
   __shared__ unsigned long long s_red64[kWavesPerBlock];
   __shared__ int32_t s_wit[kWavesPerBlock];
@@ -560,8 +593,6 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
   W.r0 = min(rb1, rb0 + (int64_t)wib * rows_per_wave);
   W.r1 = min(rb1, W.r0 + rows_per_wave);
   W.we0 = W.we1 = 0;
-#pragma unroll
-  for (int j = 0; j < kResRowsPerLane; ++j) W.own[j] = 0;
   {
     const int32_t eb0 = a.row_ptr[rb0], eb1 = a.row_ptr[rb1];
     W.resident = !a.force_stream && a.n <= (1 << 24) && rows_per_wave <= kResWaveRows &&
@@ -579,7 +610,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     }
     __syncthreads();
     if (W.resident) {
-      sort_gather_batches(S.res, W.we0, W.we1, lane);
+      sort_gather_batches(W.we0, W.we1, lane);
       __syncthreads();
     }
   }
@@ -609,9 +640,8 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
   };
   // Reads of a completed set (after the barrier that closed it).
   auto read_count = [&](int set) {
-    uint32_t t = 0;
-    for (int i = 0; i < kStripes; ++i) t += ld_agent(&c->sets[set][i].count);
-    return t;
+    uint32_t t = lane < kStripes ? ld_agent(&c->sets[set][lane].count) : 0u;
+    return wave_sum_u32(t);
   };
   // Any wave of the block changed a row: one flag per block for the barrier.
   auto block_any = [&](uint32_t ch) {
@@ -623,7 +653,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     return any ? 1u : 0u;
   };
 
-  uint32_t count_prev = 0;  // |A_k| of the current iteration
+  uint32_t count_prev = 0;  // |A_k| of the last completed iteration
   int32_t k = 0;
   int64_t total_sweeps = 0;
   int32_t status = MAP_OK, found = 0, witness = 0;
@@ -631,65 +661,101 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
   bool acc_from_pv = false;  // acc_out comes from the accepting bits of the packed values
   bool ok = true;
   uint32_t tot = 0;
+  // Asynchronous sweeps need the iteration tag; without it (n >= 2^30) every
+  // sweep ends with a grid barrier.
+  constexpr bool sync = !kAsync;
 
-  if (!a.propagate) {
-    // A_1 -> working flags; count |A_1|.
+  {
+    // Own packed values start in iteration 0 (tag 0), so no value left in the
+    // workspace by an earlier call is mistaken for one of this call; A_1 is
+    // copied to the working flags and counted.
     uint32_t cnt = 0;
     for (int64_t v = W.r0 + lane; v < W.r1; v += kWave) {
-      uint8_t x = a.acc_in[v] ? 1 : 0;
-      a.accw[v] = x;
-      cnt += x;
+      a.pv[v] = 0u;
+      if (!a.propagate) {
+        uint8_t x = a.acc_in[v] ? 1 : 0;
+        a.accw[v] = x;
+        cnt += x;
+      }
     }
     block_add_count(cnt, g.gen % kSets);
     ok = grid_sync(g, 0, nullptr);
     if (!ok) goto aborted;
     count_prev = read_count((g.gen - 1) % kSets);
-    if (count_prev == 0) { left = 0; goto done; }
+    if (!a.propagate && count_prev == 0) { left = 0; goto done; }
   }
 
   for (;;) {
-    // First sweep of an iteration: map from 0, accepting flags from acc.
-    uint32_t nacc = 0;
-    uint32_t ch = sweep_rows<true>(a, acc, W, S, wib, lane, &nacc);
-    if (!a.propagate) block_add_count(nacc, g.gen % kSets);
-    ok = grid_sync(g, block_any(ch), &tot);
-    if (!ok) goto aborted;
-    if (!a.propagate) {
-      uint32_t cnt = read_count((g.gen - 1) % kSets);
-      if (k > 0) {
-        // Iteration k is complete: |Del_k| = |A_k| - |A_{k+1}|.
-        if (b == 0 && threadIdx.x == 0 && a.trace && k <= a.trace_cap)
-          a.trace[(int64_t)(k - 1) * 3 + 0] = (uint64_t)(count_prev - cnt);
-        if (cnt == 0 || cnt == count_prev) { left = (int32_t)cnt; break; }  // no accepting left / none removed
-        if (a.max_iter > 0 && k >= a.max_iter) { status = MAP_ENOTCONVERGED; left = (int32_t)cnt; break; }
-      }
-      count_prev = cnt;
-    }
     k++;
-    int64_t s = 1;
-    if (a.sync_sweeps || nb == 1) {
-      while (tot != 0) {
-        if (s > (int64_t)a.n + 1) { status = MAP_ENOTCONVERGED; break; }
-        uint32_t c2 = sweep_rows<false>(a, acc, W, S, wib, lane, nullptr);
-        s++;
-        ok = grid_sync(g, block_any(c2), &tot);
-        if (!ok) goto aborted;
+    // Iteration tag: values written in iteration k carry the parity of k; a
+    // reader that finds the other parity takes the reset value instead.
+    const uint32_t cur = (k & 1) ? a.par_bit : 0u;
+    uint32_t nacc = 0;       // accepting rows of this block in A_k (reset sweep)
+    uint32_t cnt_k = 0;      // |A_k|
+    int64_t s = 0;           // sweeps of this block in iteration k
+    // One loop for both fixpoint controls, so that each sweep variant is
+    // inlined once.
+    //  - sync: a grid barrier after every sweep carries the changed count.
+    //  - asynchronous (the reset is each block's first sweep): blocks sweep
+    //    their rows without waiting for one another; values only grow, so
+    //    reads of stale remote values are safe.  A sweep that changed
+    //    something releases its writes and bumps `dirty`; a sweep that changed
+    //    nothing, started after reading dirty == d (then an acquire), reports
+    //    quiet {k, d+1}.  When every block reports quiet for the current value
+    //    of `dirty`, no change happened while any of those sweeps ran and every
+    //    change before them was visible to them, so all rows are at the
+    //    fixpoint: block 0 then publishes done = k.
+    const uint32_t tag = (uint32_t)k;
+    uint32_t d_seen = 0xffffffffu;  // async: counter value of this block's last quiet sweep (wave 0)
+    // After a sweep: the barrier (sync) or the change / quiet report (async).
+    // Returns false when the launch must stop.
+    auto report = [&](uint32_t any, uint32_t d0) -> bool {
+      if (sync) {
+        if (s == 1 && !a.propagate) block_add_count(nacc, g.gen % kSets);
+        if (!grid_sync(g, any, &tot)) return false;
+        if (s == 1 && !a.propagate) cnt_k = read_count((g.gen - 1) % kSets);
+        return true;
       }
-    } else if (tot != 0) {
-      // Asynchronous fixpoint.  Blocks sweep their rows without waiting for one
-      // another; values only grow, so reads of stale remote values are safe.
-      // A sweep that changed something releases its writes and bumps `dirty`;
-      // a sweep that changed nothing, started after reading dirty == d (then an
-      // acquire), reports quiet {k, d+1}.  When every block reports quiet for
-      // the current value of `dirty`, no change happened while any of those
-      // sweeps ran and every change before them was visible to them, so all
-      // rows are at the fixpoint: block 0 then publishes done = k.
-      const uint32_t tag = (uint32_t)(a.propagate ? 1 : k);
-      uint32_t d_seen = 0xffffffffu;  // counter value of this block's last quiet sweep (wave 0)
-      int64_t local = 1;
-      for (;;) {
+      if (threadIdx.x == 0) {
+        if (any) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          __hip_atomic_fetch_add(&c->dirty, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          __hip_atomic_store(&c->quiet[b], ((unsigned long long)tag << 32) | (uint32_t)(d0 + 1u),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      if (wib == 0) d_seen = any ? 0xffffffffu : d0;
+      if (s > 4 * (int64_t)a.n + 16) {  // unreachable for a monotone fixpoint: safety net
+        if (threadIdx.x == 0) st_agent((uint32_t*)&c->abort, 1u);
+        return false;
+      }
+      return true;
+    };
+    {
+      // The reset sweep of iteration k.
+      uint32_t d0 = 0;
+      if (!sync) {
+        if (threadIdx.x == 0) {
+          s_red[1] = ld_agent(&c->dirty);
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        d0 = s_red[1];
+        __syncthreads();
+      }
+      const uint32_t c1 = sweep_rows<true>(a, acc, W, wib, lane, cur, &nacc);
+      s = 1;
+      if (!report(block_any(c1), d0)) goto aborted;
+    }
+    for (;;) {
+      uint32_t d0 = 0;
+      if (sync) {
+        if (tot == 0) break;
+        if (s > (int64_t)a.n + 1) { status = MAP_ENOTCONVERGED; break; }
+      } else {
         if (wib == 0) {
-          uint32_t cmd = 0, d0 = 0;  // 0 sweep, 1 done, 2 abort
+          uint32_t cmd = 0;  // 0 sweep, 1 done, 2 abort
           const uint64_t t0 = wall_clock64();
           for (;;) {
             if (ld_agent(&c->done) == tag) { cmd = 1; break; }
@@ -717,33 +783,21 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
           }
         }
         __syncthreads();
-        const uint32_t cmd = s_red[0], d0 = s_red[1];
+        const uint32_t cmd = s_red[0];
+        d0 = s_red[1];
         __syncthreads();
         if (cmd == 2) goto aborted;
         if (cmd == 1) break;
-        const uint32_t c2 = sweep_rows<false>(a, acc, W, S, wib, lane, nullptr);
-        local++;
-        const uint32_t any = block_any(c2);
-        if (threadIdx.x == 0) {
-          if (any) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __hip_atomic_fetch_add(&c->dirty, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          } else {
-            __hip_atomic_store(&c->quiet[b], ((unsigned long long)tag << 32) | (uint32_t)(d0 + 1u),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          }
-        }
-        if (wib == 0) d_seen = any ? 0xffffffffu : d0;
-        if (local > 4 * (int64_t)a.n + 16) {  // unreachable for a monotone fixpoint: safety net
-          if (threadIdx.x == 0) st_agent((uint32_t*)&c->abort, 1u);
-          goto aborted;
-        }
       }
-      s = local;
+      const uint32_t c2 = sweep_rows<false>(a, acc, W, wib, lane, cur, nullptr);
+      s++;
+      if (!report(block_any(c2), d0)) goto aborted;
     }
-    total_sweeps += s;
-    if (status != MAP_OK) { left = (int32_t)count_prev; acc_from_pv = !a.propagate; break; }
-    if (a.propagate) break;
+    // Asynchronous mode: |A_k| is reduced together with the detect pass (same
+    // barrier epoch).
+    if (!sync && !a.propagate) block_add_count(nacc, g.gen % kSets);
+    if (status != MAP_OK) { total_sweeps += s; left = (int32_t)count_prev; acc_from_pv = !a.propagate; break; }
+    if (a.propagate) { total_sweeps += s; break; }
 
     // Detect and strip: witness = max v with map(v) == v; every nonzero map
     // value loses its accepting flag (the flags of this iteration stay in the
@@ -751,56 +805,99 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     {
       int32_t wit = 0;
       unsigned long long dig = 0;
+      uint32_t nz = 0;
       const bool want_digest = a.digest != 0;
       for_own_rows(a, W, lane, [&](int64_t v, uint32_t x) {
-        uint32_t mv = x & kValMask;
+        uint32_t mv = x & a.val_mask;
         uint32_t id = (uint32_t)v + 1u;
         if (mv == id) wit = max(wit, (int32_t)id);
         if (want_digest) dig += mix64(((unsigned long long)id << 32) | mv);
+        nz |= mv;
         // Many vertices share a map value: read before writing.
         if (mv != 0 && acc[mv - 1]) acc[mv - 1] = 0;
       });
       wit = wave_max_i32(wit);
       if (want_digest) dig = wave_sum_u64(dig);
-      if (lane == 0) { s_wit[wib] = wit; s_red64[wib] = dig; }
+      const uint32_t wnz = __ballot(nz != 0) != 0 ? 1u : 0u;
+      if (lane == 0) { s_wit[wib] = wit; s_red64[wib] = dig; s_red[wib] = wnz; }
       __syncthreads();
       if (threadIdx.x == 0) {
         int32_t bw = 0;
         unsigned long long bd = 0;
-        for (int i = 0; i < kWavesPerBlock; ++i) { bw = max(bw, s_wit[i]); bd += s_red64[i]; }
+        uint32_t bn = 0;
+        for (int i = 0; i < kWavesPerBlock; ++i) { bw = max(bw, s_wit[i]); bd += s_red64[i]; bn |= s_red[i]; }
         Stripe& st = c->sets[g.gen % kSets][b % kStripes];
         if (bw) __hip_atomic_fetch_max(&st.witness, bw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (bd) __hip_atomic_fetch_add(&st.digest, bd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (bn) __hip_atomic_fetch_add(&st.nonzero, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
+      __syncthreads();
       ok = grid_sync(g, 0, nullptr);
       if (!ok) goto aborted;
-      int set = (g.gen - 1) % kSets;
+      const int set = (g.gen - 1) % kSets;
+      // Lane i of every wave reads stripe i; the wave combines them.
       int32_t w2 = 0;
       unsigned long long d2 = 0;
-      for (int i = 0; i < kStripes; ++i) {
-        w2 = max(w2, __hip_atomic_load(&c->sets[set][i].witness, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        d2 += __hip_atomic_load(&c->sets[set][i].digest, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      uint32_t nz2 = 0, cnt2 = 0;
+      if (lane < kStripes) {
+        Stripe& st = c->sets[set][lane];
+        w2 = __hip_atomic_load(&st.witness, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        d2 = __hip_atomic_load(&st.digest, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        nz2 = ld_agent(&st.nonzero);
+        cnt2 = ld_agent(&st.count);
       }
-      if (b == 0 && threadIdx.x == 0 && a.trace && k <= a.trace_cap) {
-        uint64_t* row = a.trace + (int64_t)(k - 1) * 3;
-        row[0] = 0;
-        row[1] = (uint64_t)s;
-        row[2] = want_digest ? d2 : 0ull;
+      w2 = wave_max_i32(w2);
+      d2 = wave_sum_u64(d2);
+      nz2 = wave_sum_u32(nz2);
+      cnt2 = wave_sum_u32(cnt2);
+      if (!sync) cnt_k = cnt2;
+      const bool leader = b == 0 && threadIdx.x == 0;
+      if (k >= 2 && cnt_k == 0) {
+        // No accepting vertex was left after iteration k-1: iteration k did not happen.
+        if (leader && a.trace && k - 1 <= a.trace_cap) a.trace[(int64_t)(k - 2) * 3 + 0] = (uint64_t)count_prev;
+        k--;
+        left = 0;
+        break;
       }
-      if (w2 > 0) {
+      total_sweeps += s;
+      if (leader && a.trace) {
+        if (k >= 2 && k - 1 <= a.trace_cap) a.trace[(int64_t)(k - 2) * 3 + 0] = (uint64_t)(count_prev - cnt_k);
+        if (k <= a.trace_cap) {
+          uint64_t* row = a.trace + (int64_t)(k - 1) * 3;
+          row[0] = 0;
+          row[1] = (uint64_t)s;
+          row[2] = want_digest ? d2 : 0ull;
+        }
+      }
+      if (w2 > 0) {  // some vertex is its own maximal accepting predecessor
         found = 1;
         witness = w2;
-        left = (int32_t)count_prev;
+        left = (int32_t)cnt_k;
         acc_from_pv = true;
         break;
       }
+      if (nz2 == 0) { left = (int32_t)cnt_k; break; }  // every map value is 0: nothing to strip
+      if (a.max_iter > 0 && k >= a.max_iter) {
+        // Cap reached: count the accepting set left after this strip.
+        uint32_t cnt = 0;
+        for (int64_t v = W.r0 + lane; v < W.r1; v += kWave) cnt += a.accw[v];
+        block_add_count(cnt, g.gen % kSets);
+        ok = grid_sync(g, 0, nullptr);
+        if (!ok) goto aborted;
+        const uint32_t nxt = read_count((g.gen - 1) % kSets);
+        if (leader && a.trace && k <= a.trace_cap) a.trace[(int64_t)(k - 1) * 3 + 0] = (uint64_t)(cnt_k - nxt);
+        left = (int32_t)nxt;
+        if (nxt != 0) status = MAP_ENOTCONVERGED;
+        break;
+      }
+      count_prev = cnt_k;
     }
   }
 
 done:
   // Outputs: map vector (propagate) or the accepting set at exit (detect).
   if (a.propagate && a.map_out) {
-    for_own_rows(a, W, lane, [&](int64_t v, uint32_t x) { a.map_out[v] = (int32_t)(x & kValMask); });
+    for_own_rows(a, W, lane, [&](int64_t v, uint32_t x) { a.map_out[v] = (int32_t)(x & a.val_mask); });
   }
   if (!a.propagate && a.acc_out) {
     for_own_rows(a, W, lane, [&](int64_t v, uint32_t x) {
@@ -825,13 +922,14 @@ aborted:
   __syncthreads();
 }
 
+template <bool kAsync>
 __global__ void __launch_bounds__(kBlock) map_loop_kernel(LoopArgs a) {
   const int nb = gridDim.x;
   const int b = blockIdx.x;
   // XCD-aware numbering: consecutive hardware block ids land on different
   // XCDs; give each XCD a contiguous range of logical blocks (and rows).
   const int logical = (nb % kMaxGroups == 0) ? (b % kMaxGroups) * (nb / kMaxGroups) + b / kMaxGroups : b;
-  map_body<Ctrl>(a, a.ctrl, nb, b, logical);
+  map_body<Ctrl, kAsync>(a, a.ctrl, nb, b, logical);
 }
 
 // ------------------------------------------------------------------ batch --
@@ -851,8 +949,11 @@ struct BatchArgs {
 
 // One graph of a batch, out of line so that its register allocation is not
 // shared with the work-queue loop around it.
-__device__ __noinline__ void map_body_gang(const LoopArgs& a, GangCtrl* c, int nb, int rank) {
-  map_body<GangCtrl>(a, c, nb, rank, rank);
+__device__ __noinline__ void map_body_gang_async(const LoopArgs& a, GangCtrl* c, int nb, int rank) {
+  map_body<GangCtrl, true>(a, c, nb, rank, rank);
+}
+__device__ __noinline__ void map_body_gang_sync(const LoopArgs& a, GangCtrl* c, int nb, int rank) {
+  map_body<GangCtrl, false>(a, c, nb, rank, rank);
 }
 
 // Persistent work queue over the graphs of a batch.  Graph g is solved by
@@ -911,7 +1012,10 @@ __global__ void __launch_bounds__(kBlock) map_batch_kernel(BatchArgs ba) {
     a.digest = 0;
     a.force_stream = (ba.flags & MAP_FLAG_STREAM) ? 1 : 0;
     a.sync_sweeps = (ba.flags & MAP_FLAG_SYNC_SWEEPS) ? 1 : 0;
-    map_body_gang(a, ba.gctrl + gi, nb, rank);
+    a.val_mask = d.n < (1 << 30) ? 0x3fffffffu : kValMask;
+    a.par_bit = d.n < (1 << 30) ? 0x40000000u : 0u;
+    if (nb > 1 && !a.sync_sweeps && a.par_bit) map_body_gang_async(a, ba.gctrl + gi, nb, rank);
+    else map_body_gang_sync(a, ba.gctrl + gi, nb, rank);
   }
 }
 
@@ -1116,7 +1220,7 @@ int device_info(DeviceInfo* out) {
     int cus = 0, coop = 0, nb = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return MAP_EDEVICE;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) return MAP_EDEVICE;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(map_loop_kernel), kBlock,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(map_loop_kernel<true>), kBlock,
                                                      0) != hipSuccess)
       return MAP_EDEVICE;
     if (cus <= 0 || nb <= 0) return MAP_EDEVICE;
@@ -1143,8 +1247,10 @@ int launch_loop(LoopArgs& a, hipStream_t stream) {
                      (int64_t)(kCtrlBytes / 4), 0u);
   if (hipGetLastError() != hipSuccess) return MAP_EDEVICE;
   void* args[] = {&a};
-  if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(map_loop_kernel), dim3((unsigned)grid),
-                                 dim3(kBlock), args, 0, stream) != hipSuccess)
+  const bool async = grid > 1 && !a.sync_sweeps && a.par_bit != 0;
+  const void* kernel = async ? reinterpret_cast<const void*>(map_loop_kernel<true>)
+                             : reinterpret_cast<const void*>(map_loop_kernel<false>);
+  if (hipLaunchCooperativeKernel(kernel, dim3((unsigned)grid), dim3(kBlock), args, 0, stream) != hipSuccess)
     return MAP_EDEVICE;
   return MAP_OK;
 }
@@ -1258,6 +1364,8 @@ static int loop_common(int32_t n, const int32_t* row_ptr, const int32_t* col, co
   a.accw = reinterpret_cast<uint8_t*>(w + L.accw);
   a.ctrl = reinterpret_cast<Ctrl*>(w + L.ctrl);
   a.result = result;
+  a.val_mask = n < (1 << 30) ? 0x3fffffffu : kValMask;
+  a.par_bit = n < (1 << 30) ? 0x40000000u : 0u;
   return MAP_OK;
 }
 
