@@ -121,9 +121,9 @@ def bench_batch(args):
     def make(gang):
         return mc.Batch(o_csrs, o_accs, gang=gang, device=dev)
 
-    per_gang, timings = autotune.tune(make, o_ns, o_ms, torch.cuda.get_device_name(0), use_cache=False,
-                                      log=lambda x: print(x, file=sys.stderr, flush=True))
-    gang = autotune.gang_sizes(o_ms, per_gang)
+    policy, timings = autotune.tune(make, o_ns, o_ms, torch.cuda.get_device_name(0), use_cache=False,
+                                    log=lambda x: print(x, file=sys.stderr, flush=True))
+    gang = autotune.gang_sizes(o_ns, o_ms, policy)
     b = make(gang)
     for _ in range(args.warmup):
         b.launch()
@@ -191,7 +191,7 @@ def bench_batch(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": WORKLOADS["c4"][0], "key": "c4", "graphs": count, "sum_n": int(sum(ns)),
                    "sum_m": int(sum(ms)), "parallelism": "single GPU", "order": "largest first",
-                   "per_gang": per_gang},
+                   "gang_policy": autotune.policy_name(policy)},
         "plain_graphs_per_s": round(count / t_plain, 2), "plain_ms": round(t_plain * 1e3, 3),
         "speedup_vs_plain": round(t_plain / t_batch, 3),
         "hipgraph_graphs_per_s": round(count / t_graph, 2) if t_graph else None,
@@ -229,10 +229,23 @@ def bench_serve(args):
     qps = args.rho * rate
     print(f"[bench] serial saturated {rate:.2f} graphs/s -> offered load {qps:.2f} queries/s", file=sys.stderr,
           flush=True)
+    # gang policy: tuned on the sample served as one batch (outside the timed stream)
+    if args.serve_policy == "tune":
+        import paper_0912_2555_amd as mc
+        s_csrs = [mc.build_csr(q.n, q.src, q.dst, transposed=False) for q in sample]
+        s_accs = [torch.from_numpy(q.acc).cuda() for q in sample]
+        order = sorted(range(len(sample)), key=lambda i: -sample[i].m)
+        policy, _ = autotune.tune(lambda gang: mc.Batch([s_csrs[i] for i in order], [s_accs[i] for i in order],
+                                                        gang=gang),
+                                  [sample[i].n for i in order], [sample[i].m for i in order],
+                                  torch.cuda.get_device_name(0), use_cache=False,
+                                  log=lambda x: print(x, file=sys.stderr, flush=True))
+        del s_csrs, s_accs
+    else:
+        policy = autotune.parse_policy(args.serve_policy)
     qs = queries()
     srv = serve.Server(hbm_budget=32 << 30, max_inflight=2,
-                       gang_policy=lambda ms: autotune.gang_sizes(ms, args.serve_per_gang)
-                       if args.serve_per_gang else None)
+                       gang_policy=(lambda ns, ms: autotune.gang_sizes(ns, ms, policy)) if policy else None)
     st = serve.run_stream(qs, qps=qps, server=srv, gaps=gaps)
     ser, ser_res = serve.run_serial(queries(), qps=qps, gaps=gaps)
     exact = all(q.result.status == 0 and q.result.verdict == r.verdict and q.result.accepting_left == r.accepting_left
@@ -243,13 +256,36 @@ def bench_serve(args):
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": WORKLOADS["c5"][0], "key": "c5", "queries": count, "rho": args.rho,
                    "offered_qps": round(qps, 3), "hbm_budget_gib": 32, "max_inflight": 2,
-                   "per_gang": args.serve_per_gang, "parallelism": "single GPU"},
+                   "gang_policy": autotune.policy_name(policy), "parallelism": "single GPU"},
         "serving": {k: round(v, 3) if isinstance(v, float) else v for k, v in st.items()},
         "serial_plain": {k: round(v, 3) for k, v in ser.items()},
         "serial_saturated_graphs_per_s": round(rate, 3),
         "exact_vs_serial": exact,
     }
     print(json.dumps(out), flush=True)
+
+
+def counted_traffic(workload: str, flags: int):
+    """HBM bytes per launch from the committed counter summary, or None.
+
+    The figure holds only for the workload and flags it was taken with and for
+    the kernel source it was taken on; any other case reports None.
+    """
+    import hashlib
+    import paper_0912_2555_amd as mc
+    path = os.path.join(ROOT, "profiles", f"map_loop_kernel_{workload}_traffic.md")
+    if not os.path.exists(path) or flags != mc.MAP_FLAG_NO_TRACE_DIGEST:
+        return None
+    kv = {}
+    for line in open(path):
+        key, sep, val = line.strip().partition(": ")
+        if sep and key in ("source_sha256", "traffic_bytes_per_launch", "workload"):
+            kv[key] = val.strip()
+    src = os.path.join(ROOT, "paper_0912_2555_amd", "csrc", "mapcheck.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if kv.get("workload") != workload or kv.get("source_sha256") != digest:
+        return None
+    return int(kv["traffic_bytes_per_launch"])
 
 
 def calibrate_copy(args):
@@ -281,7 +317,8 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--serve-count", type=int, default=1000, help="queries in the config-5 stream")
     ap.add_argument("--rho", type=float, default=0.9, help="offered load / serial saturated throughput")
-    ap.add_argument("--serve-per-gang", type=int, default=1 << 18, help="edges per workgroup when serving (0: one)")
+    ap.add_argument("--serve-policy", default="tune",
+                    help="gang policy when serving: tune, one, or EDGES[+fit] (edges per workgroup)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -370,7 +407,7 @@ def main():
         "gteps_scan": round(r.sweeps * m / (detect_ms * 1e-3) / 1e9, 4),
         "roofline": {"bound": "hbm", "kernel": "map_loop_kernel", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None,
+                     "traffic": counted_traffic(args.workload, flags),
                      "bytes_per_launch": int(alg_bytes)},
     }
     if not args.no_cpu_baseline:

@@ -157,7 +157,8 @@ size_t map_batch_workspace_bytes(int32_t count, int64_t total_n, uint32_t flags)
 /*
  * The MAP outer loop (as map_detect) for many independent graphs in one
  * persistent launch: a device work queue hands each graph to a gang of
- * gang[g] workgroups (1..64; NULL = 1 for every graph), in the order given
+ * gang[g] workgroups (clamped to 1..min(256, workgroups in the launch, i.e.
+ * one per compute unit); NULL = 1 for every graph), in the order given
  * (put the largest graphs first).  With gang == NULL no workgroup ever waits
  * on another, so the launch is an ordinary one and can be captured in a HIP
  * graph; otherwise it is a cooperative launch.

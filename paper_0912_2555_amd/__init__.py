@@ -274,4 +274,5 @@ class Batch:
                                 stream), "map_detect_batch")
 
     def read(self):
-        return [Result.from_tensor(self.results[i]) for i in range(self.count)]
+        host = self.results.cpu()
+        return [Result.from_tensor(host[i]) for i in range(self.count)]

@@ -13,7 +13,8 @@
 // Device data layout (workspace):
 //   ctrl   control block: grid-barrier counters and per-epoch reduction slots;
 //   pv     uint32[n]: bit 31 = vertex is accepting in the current iteration,
-//          bits 0..30 = current map value (id, 0 = none);
+//          bit 30 = parity of the iteration that wrote the word (n < 2^30),
+//          low bits = current map value (id, 0 = none);
 //   accw   uint8[n]: working accepting flags, stripped between iterations.
 //
 // One cooperative persistent kernel runs the whole outer loop (reset, sweeps
@@ -21,6 +22,7 @@
 // phases; the host enqueues one launch per call and never synchronizes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdint>
 #include <cstring>
@@ -58,7 +60,7 @@ constexpr int kStripes = 16;
 constexpr int kSets = 3;
 constexpr int kMaxGroups = 8;  // barrier arrival groups (one per XCD)
 constexpr int kMaxBlocks = 2048;  // upper bound on the loop kernel's grid
-constexpr int kMaxGang = 64;      // upper bound on the blocks that share one graph of a batch
+constexpr int kMaxGang = 256;     // upper bound on the blocks that share one graph of a batch
 // Bound on one barrier wait, in ticks of the 100 MHz device wall clock (10 s):
 // far beyond any legitimate phase, so a broken launch exits instead of hanging.
 constexpr uint64_t kWaitTicks = 1000000000ull;
@@ -1023,7 +1025,8 @@ __global__ void __launch_bounds__(kBlock) map_batch_kernel(BatchArgs ba) {
 // and the scratch size check.
 __global__ void __launch_bounds__(1024) batch_plan(int32_t count, const map_graph_desc* graphs,
                                                    const int32_t* gang, int32_t* item_start, int64_t* scratch_off,
-                                                   size_t scratch_bytes, int32_t* status, uint32_t* next_item) {
+                                                   size_t scratch_bytes, int32_t max_gang, int32_t* status,
+                                                   uint32_t* next_item) {
   __shared__ int64_t part_i[1024];
   __shared__ int64_t part_b[1024];
   const int64_t per = ((int64_t)count + 1023) / 1024;
@@ -1031,7 +1034,7 @@ __global__ void __launch_bounds__(1024) batch_plan(int32_t count, const map_grap
   int64_t si = 0, sb = 0;
   for (int64_t i = lo; i < hi; ++i) {
     int32_t gsz = gang ? gang[i] : 1;
-    gsz = max(1, min(gsz, kMaxGang));
+    gsz = max(1, min(gsz, max_gang));
     si += gsz;
     const int64_t n = max(graphs[i].n, 1);
     sb += (int64_t)((n * 4 + 255) & ~255) + (int64_t)((n + 255) & ~255);
@@ -1053,7 +1056,7 @@ __global__ void __launch_bounds__(1024) batch_plan(int32_t count, const map_grap
     item_start[i] = (int32_t)pi;
     scratch_off[i] = pb;
     int32_t gsz = gang ? gang[i] : 1;
-    pi += max(1, min(gsz, kMaxGang));
+    pi += max(1, min(gsz, max_gang));
     const int64_t n = max(graphs[i].n, 1);
     pb += (int64_t)((n * 4 + 255) & ~255) + (int64_t)((n + 255) & ~255);
   }
@@ -1440,11 +1443,12 @@ int map_detect_batch(int32_t count, const map_graph_desc* graphs, const int32_t*
   const int64_t ctrl_words = (int64_t)((size_t)count * kGangCtrlBytes / 4);
   hipLaunchKernelGGL(fill_u32, dim3(grid_for(ctrl_words, 256)), dim3(256), 0, st,
                      reinterpret_cast<uint32_t*>(ba.gctrl), ctrl_words, 0u);
+  // A gang must fit in the grid at once: its blocks wait for each other.
+  const int grid = cus * per_cu;
   hipLaunchKernelGGL(batch_plan, dim3(1), dim3(1024), 0, st, count, graphs, gang,
                      const_cast<int32_t*>(ba.item_start), const_cast<int64_t*>(ba.scratch_off),
-                     (size_t)(L.total - L.scratch), ba.status, ba.next_item);
+                     (size_t)(L.total - L.scratch), (int32_t)std::min(kMaxGang, grid), ba.status, ba.next_item);
   if (hipGetLastError() != hipSuccess) return MAP_EDEVICE;
-  const int grid = cus * per_cu;
   if (gang == nullptr) {
     hipLaunchKernelGGL(map_batch_kernel, dim3(grid), dim3(kBlock), 0, st, ba);
     if (hipGetLastError() != hipSuccess) return MAP_EDEVICE;

@@ -72,7 +72,7 @@ class Server:
         self.budget = hbm_budget
         self.used = 0
         self.max_inflight = max_inflight
-        self.gang_policy = gang_policy      # callable(list of m) -> list of gang sizes, or None
+        self.gang_policy = gang_policy      # callable(list of n, list of m) -> gang sizes, or None
         self.device = torch.device(device)
         self.upload = torch.cuda.Stream(device=self.device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(max_inflight)]
@@ -128,7 +128,7 @@ class Server:
         ready.sort(key=lambda q: -q.m)                           # largest first
         self.admitted = [q for q in self.admitted if q not in ready]
         stream = self.free_streams.popleft()
-        gang = self.gang_policy([q.m for q in ready]) if self.gang_policy else None
+        gang = self.gang_policy([q.n for q in ready], [q.m for q in ready]) if self.gang_policy else None
         with torch.cuda.stream(stream):
             # descriptors, results and workspace are allocated and uploaded on
             # the launch stream, so the launch is ordered after them

@@ -52,7 +52,7 @@ def test_serving_with_gangs(mods):
     refs = [oracle.map_detect(g, mode="desc") for g in gs]
     qs = [serve.Query(i, g.n, g.src, g.dst, g.acc) for i, g in enumerate(gs)]
     srv = serve.Server(hbm_budget=1 << 30, max_inflight=2,
-                       gang_policy=lambda ms: autotune.gang_sizes(ms, 1 << 17))
+                       gang_policy=lambda ns, ms: autotune.gang_sizes(ns, ms, (1 << 17, True)))
     serve.run_stream(qs, qps=500.0, server=srv)
     for q, ref in zip(qs, refs):
         assert q.result.status == 0 and q.result.verdict == ref.verdict
