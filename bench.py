@@ -40,7 +40,8 @@ WORKLOADS = {
     "c1b": ("config 1 DAG instance: high->low edges of the config-1 draw", "config1", True),
     "c3": ("config 3: N=2^25 DAG, ~134M edges, 0.1% accepting, no accepting cycle", "config3", None),
     "c5": ("config 5: Poisson stream of config-1 DAG queries, N log-uniform in [1e4,4e6], accepting ratio "
-           "U[0.1%,5%], odd ones planted; continuous batching under a 32 GiB HBM budget vs a serial plain loop",
+           "U[0.1%,5%], odd ones planted; continuous batching on one persistent engine under a 32 GiB HBM budget "
+           "vs a serial plain loop",
            "config5", None),
     "c4": ("config 4: 4,096 independent config-1 DAG graphs, N log-uniform in [1e3,1e6], odd ones with a "
            "planted accepting 64-cycle, one persistent launch vs the plain per-graph loop", "config4", None),
@@ -205,8 +206,13 @@ def bench_batch(args):
 
 
 def bench_serve(args):
-    """Serving: Poisson arrivals at rho x the serial plain throughput; p50/p99 and graphs/s."""
+    """Serving: Poisson arrivals at rho x the serial plain throughput; p50/p99 and graphs/s.
+
+    Query payloads (edge lists, flags) sit in pinned host memory, as a receive
+    buffer would; the serial baseline and the server read the same buffers.
+    """
     import torch
+    import paper_0912_2555_amd as mc
     from paper_0912_2555_amd import autotune, serve
     import synth
 
@@ -215,11 +221,13 @@ def bench_serve(args):
     t0 = time.perf_counter()
     graphs = [synth.config5(i) for i in range(count)]
     gaps = [synth.config5_meta(i)[2] for i in range(count)]
-    print(f"[bench] c5: {count} queries, sum n={sum(g.n for g in graphs)}, generated in "
-          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    pinned = [(torch.from_numpy(g.src).pin_memory(), torch.from_numpy(g.dst).pin_memory(),
+               torch.from_numpy(g.acc).pin_memory()) for g in graphs]
+    print(f"[bench] c5: {count} queries, sum n={sum(g.n for g in graphs)}, sum m={sum(g.m for g in graphs)}, "
+          f"generated and pinned in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 
     def queries():
-        return [serve.Query(i, g.n, g.src, g.dst, g.acc) for i, g in enumerate(graphs)]
+        return [serve.Query(i, g.n, p[0], p[1], p[2]) for i, (g, p) in enumerate(zip(graphs, pinned))]
 
     # serial plain throughput, saturated (back-to-back), on a sample
     sample = queries()[:min(count, 64)]
@@ -229,11 +237,11 @@ def bench_serve(args):
     qps = args.rho * rate
     print(f"[bench] serial saturated {rate:.2f} graphs/s -> offered load {qps:.2f} queries/s", file=sys.stderr,
           flush=True)
-    # gang policy: tuned on the sample served as one batch (outside the timed stream)
+
+    # gang policy: tuned on the sample solved as one batch (before serving)
     if args.serve_policy == "tune":
-        import paper_0912_2555_amd as mc
         s_csrs = [mc.build_csr(q.n, q.src, q.dst, transposed=False) for q in sample]
-        s_accs = [torch.from_numpy(q.acc).cuda() for q in sample]
+        s_accs = [q.acc.cuda() for q in sample]
         order = sorted(range(len(sample)), key=lambda i: -sample[i].m)
         policy, _ = autotune.tune(lambda gang: mc.Batch([s_csrs[i] for i in order], [s_accs[i] for i in order],
                                                         gang=gang),
@@ -243,24 +251,42 @@ def bench_serve(args):
         del s_csrs, s_accs
     else:
         policy = autotune.parse_policy(args.serve_policy)
-    qs = queries()
-    srv = serve.Server(hbm_budget=32 << 30, max_inflight=2,
-                       gang_policy=(lambda ns, ms: autotune.gang_sizes(ns, ms, policy)) if policy else None)
-    st = serve.run_stream(qs, qps=qps, server=srv, gaps=gaps)
+    gang_policy = (lambda ns, ms: autotune.gang_sizes(ns, ms, policy)) if policy else None
+    torch.cuda.synchronize()
+
+    budget = 32 << 30
+    with serve.Server(hbm_budget=budget, gang_policy=gang_policy) as srv:
+        warm = queries()[:16]
+        serve.run_stream(warm, qps=1e9, server=srv)             # warm-up
+        qs = queries()
+        st = serve.run_stream(qs, qps=qps, server=srv, gaps=gaps)
+        over = None
+        if args.rho_over > 0:
+            qo = queries()
+            over = serve.run_stream(qo, qps=args.rho_over * rate, server=srv, gaps=gaps)
+        qsat = queries()
+        sat_engine = serve.run_stream(qsat, qps=1e9, server=srv)  # everything at once: engine capacity
+        max_running = srv.max_running
+        workgroups = srv.engine.workgroups
     ser, ser_res = serve.run_serial(queries(), qps=qps, gaps=gaps)
     exact = all(q.result.status == 0 and q.result.verdict == r.verdict and q.result.accepting_left == r.accepting_left
                 for q, r in zip(qs, ser_res))
+    exact_sat = all(a.result.verdict == b.result.verdict for a, b in zip(qsat, qs))
+    rnd = lambda d: {k: round(v, 3) if isinstance(v, float) else v for k, v in d.items()}
     out = {
         "metric": METRIC, "value": round(st["graphs_per_s"], 3), "unit": "graphs/s", "n_gpus": 1, "steps": 1,
         "warmup": 1, "ms_per_step": round(st["span_s"] * 1e3, 1), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": WORKLOADS["c5"][0], "key": "c5", "queries": count, "rho": args.rho,
-                   "offered_qps": round(qps, 3), "hbm_budget_gib": 32, "max_inflight": 2,
+                   "offered_qps": round(qps, 3), "hbm_budget_gib": budget >> 30, "engine_workgroups": workgroups,
                    "gang_policy": autotune.policy_name(policy), "parallelism": "single GPU"},
-        "serving": {k: round(v, 3) if isinstance(v, float) else v for k, v in st.items()},
-        "serial_plain": {k: round(v, 3) for k, v in ser.items()},
+        "serving": rnd(st),
+        "serial_plain": rnd(ser),
         "serial_saturated_graphs_per_s": round(rate, 3),
-        "exact_vs_serial": exact,
+        "engine_saturated": rnd(sat_engine),
+        "overload": ({"rho": args.rho_over, **rnd(over)} if over else None),
+        "max_queries_on_engine": max_running,
+        "exact_vs_serial": exact, "exact_saturated_vs_stream": exact_sat,
     }
     print(json.dumps(out), flush=True)
 
@@ -317,6 +343,7 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--serve-count", type=int, default=1000, help="queries in the config-5 stream")
     ap.add_argument("--rho", type=float, default=0.9, help="offered load / serial saturated throughput")
+    ap.add_argument("--rho-over", type=float, default=1.5, help="second, overloaded stream (0: skip)")
     ap.add_argument("--serve-policy", default="tune",
                     help="gang policy when serving: tune, one, or EDGES[+fit] (edges per workgroup)")
     args = ap.parse_args()

@@ -22,10 +22,11 @@
  *   - Accepting flags are uint8[n]; entry i (nonzero = accepting) is id i+1.
  *   - 1 <= n <= 2^31 - 2 and 0 <= m <= 2^31 - 1, else MAP_ERANGE.
  *   - Pointers marked "device" must be device memory (hipMalloc or a torch
- *     CUDA tensor) of the stated length, owned by the caller.  The library
- *     never allocates or frees device memory; scratch comes from the caller's
- *     workspace `ws` of at least map_workspace_bytes(n, m, flags) bytes,
- *     256-byte aligned.
+ *     CUDA tensor) of the stated length, owned by the caller.  Apart from the
+ *     serving engine (map_engine_create allocates its own queue and control
+ *     state, map_engine_destroy frees them) the library never allocates or
+ *     frees memory; scratch comes from the caller's workspace `ws` of at least
+ *     map_workspace_bytes(n, m, flags) bytes, 256-byte aligned.
  *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Every
  *     call only enqueues work on it and returns; nothing synchronizes.  Device
  *     outputs are valid once the stream has been synchronized.
@@ -55,6 +56,8 @@ extern "C" {
 #define MAP_EDEVICE (-4)       /* the HIP runtime refused a launch */
 #define MAP_ENOTCONVERGED (-5) /* device: iteration or sweep cap reached */
 #define MAP_ERANGE_DEV (-6)    /* device: an edge endpoint outside 1..n */
+#define MAP_EBUSY (-7)         /* engine: no free job slot or ticket space */
+#define MAP_PENDING 1          /* engine: the job has not finished yet */
 
 /* Flags (bitwise or; 0 = automatic choice). */
 #define MAP_FLAG_DENSE_ONLY 0x1u /* never switch to the sparse (frontier) sweep */
@@ -170,6 +173,88 @@ size_t map_batch_workspace_bytes(int32_t count, int64_t total_n, uint32_t flags)
  */
 int map_detect_batch(int32_t count, const map_graph_desc *graphs, const int32_t *gang, map_result *results,
                      int64_t total_n, uint32_t flags, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Serving engine: one persistent launch that takes jobs while it runs.
+ *
+ * The MAP outer loop of map_detect, for graphs that arrive while others are
+ * being checked (continuous batching).  map_engine_create launches a
+ * cooperative kernel that stays on the device until map_engine_stop; the host
+ * posts jobs into fine-grained host memory and the kernel's workgroups pick
+ * them up as they free up, so a job submitted while others run starts on the
+ * workgroups the earlier jobs release, with no new launch.  Each job is an edge
+ * list: its gang of workgroups builds the pull CSR (as map_build_csr) and runs
+ * the MAP loop on it (as map_detect, without trace, accepting_out or iteration
+ * cap); the result is written to host memory.  The edge list and flags may stay
+ * in pinned host memory (hipHostMalloc, torch pin_memory): the engine reads
+ * them over the bus itself, so no copy has to run beside it.
+ *
+ * While the engine runs it occupies all but `cus / 32` compute units (by
+ * default): other kernels on the device run on the rest, or wait for the
+ * engine to stop.  Calls on one engine must come from one host thread.
+ */
+typedef struct map_engine map_engine;
+
+/* One job of the engine; the engine reads it when the job starts. */
+typedef struct map_job {
+  int32_t n;                  /* vertices, ids 1..n */
+  int32_t gang;               /* workgroups for this graph; clamped to 1..min(256, engine workgroups) */
+  int64_t m;                  /* edges */
+  const int32_t *src;         /* int32[m]: edge src[i] -> dst[i], ids 1..n (device or pinned host) */
+  const int32_t *dst;         /* int32[m] (device or pinned host) */
+  int32_t *row_ptr;           /* device int32[n+1] out: pull CSR (as map_build_csr) */
+  int32_t *col;               /* device int32[m] out */
+  const uint8_t *accepting0;  /* uint8[n]: A_1, not modified (device or pinned host) */
+  void *scratch;              /* device, map_job_scratch_bytes(n, m) bytes, 256-byte aligned */
+  uint64_t tag;               /* free for the caller; not read by the engine */
+} map_job;
+
+/* Bytes of device scratch one job needs (0 when n or m is out of range). */
+size_t map_job_scratch_bytes(int32_t n, int64_t m);
+
+/*
+ * Start an engine on the current device.
+ *   max_jobs      1..65536 jobs in flight (submitted, not yet polled as done).
+ *   workgroups    0 = all but one compute unit in 32; else at most that many.
+ *   idle_seconds  the kernel exits by itself after this long without a job
+ *                 (every later submit returns MAP_EDEVICE); (0, 86400].
+ *   flags         MAP_FLAG_STREAM / MAP_FLAG_SYNC_SWEEPS as for map_detect.
+ *   stream        the engine kernel's stream; keep other work off it.
+ *   out           the engine handle.
+ * Returns MAP_EDEVICE when allocation or the launch fails.
+ */
+int map_engine_create(int32_t max_jobs, int32_t workgroups, double idle_seconds, uint32_t flags, void *stream,
+                      map_engine **out);
+
+/* Workgroups of the engine launch (0 for NULL). */
+int map_engine_workgroups(const map_engine *e);
+
+/*
+ * Post a job.  Every buffer it names must hold its final contents (copies into
+ * src, dst and accepting0 complete) and stay allocated until the job is polled
+ * as done.  src, dst and accepting0 must be device memory or pinned host
+ * memory; row_ptr, col and scratch device memory; anything else (pageable
+ * host memory, unknown pointers) is rejected with MAP_EINVAL before the engine
+ * sees the job.  *slot identifies the job for map_engine_poll.  Returns
+ * MAP_EBUSY when max_jobs jobs are in flight or the ticket ring is full (poll
+ * finished jobs, then retry), MAP_EDEVICE when the engine has exited,
+ * MAP_EINVAL / MAP_ERANGE for bad arguments or after map_engine_stop.
+ */
+int map_engine_submit(map_engine *e, const map_job *job, int32_t *slot);
+
+/*
+ * Non-blocking completion check.  MAP_PENDING while the job runs; MAP_OK when
+ * it has finished, with its map_result copied to *out (status MAP_OK, or
+ * MAP_ERANGE_DEV for an edge outside 1..n, or MAP_EDEVICE) and the slot freed;
+ * MAP_EDEVICE (slot freed) when the engine exited without running it.
+ */
+int map_engine_poll(map_engine *e, int32_t slot, map_result *out);
+
+/* Ask the engine to exit once every submitted job has started (returns at once). */
+int map_engine_stop(map_engine *e);
+
+/* Stop, wait until the kernel has exited, and free the engine. */
+int map_engine_destroy(map_engine *e);
 
 /* Static description of a status code. */
 const char *map_strerror(int status);

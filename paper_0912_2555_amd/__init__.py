@@ -38,13 +38,16 @@ MAP_ENOSPC = -3
 MAP_EDEVICE = -4
 MAP_ENOTCONVERGED = -5
 MAP_ERANGE_DEV = -6
+MAP_EBUSY = -7
+MAP_PENDING = 1
 MAP_FLAG_DENSE_ONLY = 0x1
 MAP_FLAG_NO_TRACE_DIGEST = 0x2
 MAP_FLAG_STREAM = 0x4
 MAP_FLAG_SYNC_SWEEPS = 0x8
 
 EXPORTS = ("map_workspace_bytes", "map_build_csr", "map_propagate", "map_detect", "map_batch_workspace_bytes",
-           "map_detect_batch", "map_strerror")
+           "map_detect_batch", "map_job_scratch_bytes", "map_engine_create", "map_engine_workgroups",
+           "map_engine_submit", "map_engine_poll", "map_engine_stop", "map_engine_destroy", "map_strerror")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_0912_2555_amd.build` "
@@ -64,6 +67,20 @@ _lib.map_batch_workspace_bytes.argtypes = [_i32, _i64, _u32]
 _lib.map_batch_workspace_bytes.restype = _sz
 _lib.map_detect_batch.argtypes = [_i32, _vp, _vp, _vp, _i64, _u32, _vp, _sz, _vp]
 _lib.map_detect_batch.restype = ctypes.c_int
+_lib.map_job_scratch_bytes.argtypes = [_i32, _i64]
+_lib.map_job_scratch_bytes.restype = _sz
+_lib.map_engine_create.argtypes = [_i32, _i32, ctypes.c_double, _u32, _vp, ctypes.POINTER(_vp)]
+_lib.map_engine_create.restype = ctypes.c_int
+_lib.map_engine_workgroups.argtypes = [_vp]
+_lib.map_engine_workgroups.restype = ctypes.c_int
+_lib.map_engine_submit.argtypes = [_vp, _vp, ctypes.POINTER(_i32)]
+_lib.map_engine_submit.restype = ctypes.c_int
+_lib.map_engine_poll.argtypes = [_vp, _i32, _vp]
+_lib.map_engine_poll.restype = ctypes.c_int
+_lib.map_engine_stop.argtypes = [_vp]
+_lib.map_engine_stop.restype = ctypes.c_int
+_lib.map_engine_destroy.argtypes = [_vp]
+_lib.map_engine_destroy.restype = ctypes.c_int
 _lib.map_strerror.argtypes = [ctypes.c_int]
 _lib.map_strerror.restype = ctypes.c_char_p
 
@@ -85,6 +102,17 @@ def _ptr(t):
         raise TypeError("expected a torch.Tensor or None")
     if not t.is_cuda:
         raise ValueError("device tensor required (torch CUDA/HIP tensor)")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor required")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _addr(t):
+    """Address of a contiguous tensor on the device or in host memory (the callee validates it)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch.Tensor or None")
     if not t.is_contiguous():
         raise ValueError("contiguous tensor required")
     return ctypes.c_void_p(t.data_ptr())
@@ -276,3 +304,94 @@ class Batch:
     def read(self):
         host = self.results.cpu()
         return [Result.from_tensor(host[i]) for i in range(self.count)]
+
+
+# ------------------------------------------------------------ serving engine
+
+class MapJob(ctypes.Structure):
+    """struct map_job (include/mapcheck.h)."""
+    _fields_ = [("n", ctypes.c_int32), ("gang", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("accepting0", ctypes.c_void_p), ("scratch", ctypes.c_void_p),
+                ("tag", ctypes.c_uint64)]
+
+
+class MapResultC(ctypes.Structure):
+    """struct map_result (include/mapcheck.h)."""
+    _fields_ = [("found", ctypes.c_int32), ("witness", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("sweeps", ctypes.c_int64), ("accepting_left", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+def map_job_scratch_bytes(n: int, m: int) -> int:
+    return int(_lib.map_job_scratch_bytes(n, m))
+
+
+class Engine:
+    """A running map_engine: jobs are submitted and polled while it stays on the device.
+
+    The engine kernel runs on its own stream until ``close()`` (or the idle
+    bound).  ``submit`` takes tensors whose contents are final: the edge list
+    and flags on the device or in pinned host memory, the CSR and scratch on
+    the device; it keeps them referenced until the job is polled as done.
+    """
+
+    def __init__(self, max_jobs: int = 1024, workgroups: int = 0, idle_seconds: float = 60.0, flags: int = 0,
+                 stream=None, device=None):
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        h = ctypes.c_void_p()
+        _check(_lib.map_engine_create(max_jobs, workgroups, float(idle_seconds), flags,
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "map_engine_create")
+        self._h = h
+        self.workgroups = int(_lib.map_engine_workgroups(h))
+        self._keep = {}
+
+    def submit(self, n, src, dst, row_ptr, col, accepting0, scratch, gang: int = 1, tag: int = 0):
+        """Post one job; returns its slot, or None when the engine is full (MAP_EBUSY)."""
+        if self._h is None:
+            raise MapError(MAP_EINVAL, "map_engine_submit")
+        m = 0 if src is None else int(src.numel())
+        job = MapJob(int(n), int(gang), m, _addr(src), _addr(dst), _addr(row_ptr), _addr(col), _addr(accepting0),
+                     _addr(scratch), int(tag))
+        slot = ctypes.c_int32(-1)
+        rc = _lib.map_engine_submit(self._h, ctypes.byref(job), ctypes.byref(slot))
+        if rc == MAP_EBUSY:
+            return None
+        _check(rc, "map_engine_submit")
+        self._keep[slot.value] = (src, dst, row_ptr, col, accepting0, scratch)
+        return slot.value
+
+    def poll(self, slot: int):
+        """Result of a finished job (its slot is freed), or None while it runs."""
+        r = MapResultC()
+        rc = _lib.map_engine_poll(self._h, int(slot), ctypes.byref(r))
+        if rc == MAP_PENDING:
+            return None
+        self._keep.pop(slot, None)
+        _check(rc, "map_engine_poll")
+        return Result(r.found, r.witness, r.iterations, r.status, r.sweeps, r.accepting_left)
+
+    def stop(self):
+        if self._h is not None:
+            _check(_lib.map_engine_stop(self._h), "map_engine_stop")
+
+    def close(self):
+        """Stop, wait for the engine kernel to exit, free it (idempotent)."""
+        if self._h is not None:
+            rc = _lib.map_engine_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+            _check(rc, "map_engine_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

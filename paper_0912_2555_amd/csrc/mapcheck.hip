@@ -27,6 +27,7 @@
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "mapcheck.h"
 
@@ -958,6 +959,34 @@ __device__ __noinline__ void map_body_gang_sync(const LoopArgs& a, GangCtrl* c, 
   map_body<GangCtrl, false>(a, c, nb, rank, rank);
 }
 
+// Loop arguments of one graph solved by a gang: scratch holds the packed
+// values (4n bytes, 256-aligned) followed by the working accepting flags.
+__device__ LoopArgs gang_args(int32_t n, const int32_t* row_ptr, const int32_t* col, const uint8_t* acc0,
+                              char* scratch, map_result* result, uint32_t flags) {
+  LoopArgs a;
+  a.n = n;
+  a.ntiles = (int32_t)(((int64_t)n + kTileRows - 1) / kTileRows);
+  a.row_ptr = row_ptr;
+  a.col = col;
+  a.acc_in = acc0;
+  a.pv = reinterpret_cast<uint32_t*>(scratch);
+  a.accw = reinterpret_cast<uint8_t*>(scratch + (((size_t)n * 4 + 255) & ~(size_t)255));
+  a.ctrl = nullptr;
+  a.result = result;
+  a.trace = nullptr;
+  a.trace_cap = 0;
+  a.acc_out = nullptr;
+  a.map_out = nullptr;
+  a.max_iter = 0;
+  a.propagate = 0;
+  a.digest = 0;
+  a.force_stream = (flags & MAP_FLAG_STREAM) ? 1 : 0;
+  a.sync_sweeps = (flags & MAP_FLAG_SYNC_SWEEPS) ? 1 : 0;
+  a.val_mask = n < (1 << 30) ? 0x3fffffffu : kValMask;
+  a.par_bit = n < (1 << 30) ? 0x40000000u : 0u;
+  return a;
+}
+
 // Persistent work queue over the graphs of a batch.  Graph g is solved by
 // item_start[g+1] - item_start[g] blocks (its gang); each block pops one item
 // (graph, rank) at a time.  Items of a gang are consecutive in the queue, so a
@@ -995,29 +1024,363 @@ __global__ void __launch_bounds__(kBlock) map_batch_kernel(BatchArgs ba) {
       continue;
     }
     char* base = ba.scratch + ba.scratch_off[gi];
-    LoopArgs a;
-    a.n = d.n;
-    a.ntiles = (int32_t)(((int64_t)d.n + kTileRows - 1) / kTileRows);
-    a.row_ptr = d.row_ptr;
-    a.col = d.col;
-    a.acc_in = d.accepting0;
-    a.pv = reinterpret_cast<uint32_t*>(base);
-    a.accw = reinterpret_cast<uint8_t*>(base + (((size_t)d.n * 4 + 255) & ~(size_t)255));
-    a.ctrl = nullptr;
-    a.result = ba.results + gi;
-    a.trace = nullptr;
-    a.trace_cap = 0;
-    a.acc_out = nullptr;
-    a.map_out = nullptr;
-    a.max_iter = 0;
-    a.propagate = 0;
-    a.digest = 0;
-    a.force_stream = (ba.flags & MAP_FLAG_STREAM) ? 1 : 0;
-    a.sync_sweeps = (ba.flags & MAP_FLAG_SYNC_SWEEPS) ? 1 : 0;
-    a.val_mask = d.n < (1 << 30) ? 0x3fffffffu : kValMask;
-    a.par_bit = d.n < (1 << 30) ? 0x40000000u : 0u;
+    const LoopArgs a = gang_args(d.n, d.row_ptr, d.col, d.accepting0, base, ba.results + gi, ba.flags);
     if (nb > 1 && !a.sync_sweeps && a.par_bit) map_body_gang_async(a, ba.gctrl + gi, nb, rank);
     else map_body_gang_sync(a, ba.gctrl + gi, nb, rank);
+  }
+}
+
+// ----------------------------------------------------------------- engine --
+//
+// A persistent server kernel: one cooperative launch that runs until the host
+// asks it to stop.  The host posts jobs (an edge list to turn into a CSR and
+// check) into fine-grained host memory; a job whose gang has g workgroups
+// takes g consecutive tickets, each naming (job slot, rank).  Workgroups take
+// tickets in order from a device counter, so, as in the batch queue, every gang
+// is completed by workgroups that free up and never waits on a later ticket.
+// Only the workgroup holding the first unpublished ticket polls host memory; it
+// mirrors the host's ticket count into device memory for the other waiters.
+
+struct EngineShared {          // fine-grained host memory, shared with the host
+  unsigned long long tail;     // tickets published by the host
+  uint32_t stop;               // host: exit once every published ticket is taken
+  uint32_t expired;            // device: the idle bound elapsed and the engine exited
+  uint32_t pad[28];
+};
+static_assert(sizeof(EngineShared) == 128, "shared block is one 128-byte line");
+
+struct alignas(128) EngineDev {  // device memory
+  unsigned long long head;       // next ticket to hand out
+  unsigned long long pad0[15];
+  unsigned long long mirror;     // the host's ticket count as last seen by the polling workgroup
+  unsigned long long pad1[15];
+  uint32_t quit;                 // 1: no further ticket will be published
+  uint32_t pad2[31];
+};
+
+struct EngineArgs {
+  EngineShared* sh;                // device address of the shared host block
+  const unsigned long long* ring;  // [ring_cap] host: (slot << 32) | rank
+  const map_job* jobs;             // [slots] host
+  map_result* hres;                // [slots] host: status MAP_PENDING until the job is done
+  EngineDev* dev;
+  GangCtrl* bctrl;                 // [slots] barriers of the CSR build
+  GangCtrl* mctrl;                 // [slots] barriers of the MAP loop
+  map_result* dres;                // [slots] device results
+  unsigned long long* ready;       // [slots] first ticket + 1 of the job whose control blocks are zeroed
+  int32_t ring_cap;
+  int32_t slots;
+  uint64_t idle_ticks;             // idle bound in device wall-clock ticks
+  uint32_t flags;
+};
+
+static_assert(sizeof(map_job) % 8 == 0, "map_job is read as 64-bit words");
+
+__device__ uint32_t block_sum_u32(uint32_t x) {
+  __shared__ uint32_t s_bs[kWavesPerBlock];
+  x = wave_sum_u32(x);
+  if ((threadIdx.x & (kWave - 1)) == 0) s_bs[threadIdx.x / kWave] = x;
+  __syncthreads();
+  uint32_t t = 0;
+  for (int i = 0; i < kWavesPerBlock; ++i) t += s_bs[i];
+  __syncthreads();
+  return t;
+}
+
+// Inclusive scan of one value per thread over the block; *total = block sum.
+__device__ uint32_t block_scan_u32(uint32_t x, uint32_t* total) {
+  __shared__ uint32_t s_ws[kWavesPerBlock];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)x, off, kWave);
+    if (lane >= off) x += y;
+  }
+  if (lane == kWave - 1) s_ws[w] = x;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+  for (int i = 0; i < kWavesPerBlock; ++i) {
+    const uint32_t v = s_ws[i];
+    pre += i < w ? v : 0u;
+    tot += v;
+  }
+  __syncthreads();
+  *total = tot;
+  return x + pre;
+}
+
+template <typename C>
+__device__ Grid<C> make_grid(C* c, int nb, int b) {
+  Grid<C> g;
+  g.c = c;
+  g.gen = 0;
+  g.nblocks = nb;
+  g.ngroups = min(nb, kMaxGroups);
+  g.group = b % g.ngroups;
+  g.group_size = nb / g.ngroups + ((b % g.ngroups) < (nb % g.ngroups) ? 1 : 0);
+  g.rank = b;
+  return g;
+}
+
+// Calls f(src[e], dst[e]) for the edges e = gt, gt + gs, ... of [0, m).  The
+// arrays may live in host memory, where every load is a bus round trip, so
+// when both are 16-byte aligned they are read four edges at a time with two
+// such loads per array in flight.
+template <typename F>
+__device__ __forceinline__ void for_edges(const int32_t* src, const int32_t* dst, int64_t m, int64_t gt,
+                                          int64_t gs, F f) {
+  int64_t e0 = 0;
+  if (((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0) {
+    const int64_t q = m / 4;
+    const int4* s4 = reinterpret_cast<const int4*>(src);
+    const int4* d4 = reinterpret_cast<const int4*>(dst);
+    int64_t i = gt;
+    for (; i + gs < q; i += 2 * gs) {
+      const int4 a = s4[i], b = d4[i], c = s4[i + gs], d = d4[i + gs];
+      f(a.x, b.x);
+      f(a.y, b.y);
+      f(a.z, b.z);
+      f(a.w, b.w);
+      f(c.x, d.x);
+      f(c.y, d.y);
+      f(c.z, d.z);
+      f(c.w, d.w);
+    }
+    if (i < q) {
+      const int4 a = s4[i], b = d4[i];
+      f(a.x, b.x);
+      f(a.y, b.y);
+      f(a.z, b.z);
+      f(a.w, b.w);
+    }
+    e0 = q * 4;
+  }
+  for (int64_t e = e0 + gt; e < m; e += gs) f(src[e], dst[e]);
+}
+
+// Pull CSR of a job's edge list, built by its gang: the same arrays that
+// map_build_csr produces, up to the order of columns inside a row.  cursor is
+// int32[n] and part uint32[nb] of scratch.  Returns false if a gang barrier
+// timed out; *bad = edges with an endpoint outside 1..n (the CSR is then
+// unspecified and the gang stops after the histogram).
+__device__ bool gang_build_csr(const map_job& j, int32_t* cursor, uint32_t* part, Grid<GangCtrl>& g, int nb,
+                               int rank, uint32_t* bad) {
+  const int32_t n = j.n;
+  const int64_t m = j.m;
+  int32_t* rp = j.row_ptr;
+  const int64_t gt = (int64_t)rank * kBlock + threadIdx.x, gs = (int64_t)nb * kBlock;
+  for (int64_t i = gt; i <= n; i += gs) rp[i] = 0;
+  if (!grid_sync(g, 0u, nullptr)) return false;
+  // Degree histogram: the count of row v (vertex v+1) lands at rp[v+1].
+  uint32_t nbad = 0;
+  for_edges(j.src, j.dst, m, gt, gs, [&](int32_t s, int32_t d) {
+    if (s < 1 || s > n || d < 1 || d > n) {
+      ++nbad;
+      return;
+    }
+    __hip_atomic_fetch_add(&rp[s], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  });
+  nbad = block_sum_u32(nbad);
+  uint32_t tot = 0;
+  if (!grid_sync(g, nbad, &tot)) return false;
+  *bad = tot;
+  if (tot) return true;
+  // Inclusive scan of rp[0..n]: chunk totals, then each block scans its chunk
+  // from the sum of the chunks before it.
+  const int64_t len = (int64_t)n + 1, chunk = (len + nb - 1) / nb;
+  const int64_t lo = min(len, (int64_t)rank * chunk), hi = min(len, lo + chunk);
+  uint32_t sum = 0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) sum += (uint32_t)rp[i];
+  sum = block_sum_u32(sum);
+  if (threadIdx.x == 0) st_agent(&part[rank], sum);
+  if (!grid_sync(g, 0u, nullptr)) return false;
+  uint32_t off = 0;
+  for (int i = threadIdx.x; i < rank; i += kBlock) off += ld_agent(&part[i]);
+  off = block_sum_u32(off);
+  for (int64_t base = lo; base < hi; base += kBlock) {
+    const int64_t i = base + threadIdx.x;
+    uint32_t piece = 0;
+    const uint32_t incl = block_scan_u32(i < hi ? (uint32_t)rp[i] : 0u, &piece);
+    if (i < hi) rp[i] = (int32_t)(off + incl);
+    off += piece;
+  }
+  if (!grid_sync(g, 0u, nullptr)) return false;
+  for (int64_t r = gt; r < n; r += gs) cursor[r] = rp[r];
+  if (!grid_sync(g, 0u, nullptr)) return false;
+  int32_t* col = j.col;
+  for_edges(j.src, j.dst, m, gt, gs, [&](int32_t s, int32_t d) {
+    const int32_t pos = __hip_atomic_fetch_add(&cursor[s - 1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    col[pos] = d - 1;
+  });
+  return grid_sync(g, 0u, nullptr);
+}
+
+// One ticket of a job: rank `rank` of its gang.  Rank 0 zeroes the job's
+// control blocks before any rank uses them, and publishes the result to host
+// memory after every other rank has left the job.
+__device__ __noinline__ void engine_job(const EngineArgs& ea, int slot, int rank, unsigned long long start) {
+  constexpr int kJobWords = (int)(sizeof(map_job) / 8);
+  __shared__ unsigned long long s_job[kJobWords];
+  __shared__ int s_ready;
+  if (threadIdx.x < kJobWords)
+    s_job[threadIdx.x] = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(ea.jobs + slot) + threadIdx.x,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __syncthreads();
+  map_job j;
+  memcpy(&j, s_job, sizeof(j));
+  const int nb = max(1, min(j.gang, min((int)gridDim.x, kMaxGang)));
+  GangCtrl* bc = ea.bctrl + slot;
+  GangCtrl* mcx = ea.mctrl + slot;
+  map_result* res = ea.dres + slot;
+  char* sc = static_cast<char*>(j.scratch);
+  const size_t pv_bytes = ((size_t)j.n * 4 + 255) & ~(size_t)255;
+  const size_t acc_bytes = ((size_t)j.n + 255) & ~(size_t)255;
+
+  if (rank == 0) {
+    uint32_t* pb = reinterpret_cast<uint32_t*>(bc);
+    uint32_t* pm = reinterpret_cast<uint32_t*>(mcx);
+    for (int i = threadIdx.x; i < (int)(kGangCtrlBytes / 4); i += kBlock) {
+      pb[i] = 0u;
+      pm[i] = 0u;
+    }
+    if (threadIdx.x < 8) reinterpret_cast<uint32_t*>(res)[threadIdx.x] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(ea.ready + slot, start + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_ready = 1;
+    }
+  } else if (threadIdx.x == 0) {
+    int ok = 1;
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(ea.ready + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != start + 1) {
+      __builtin_amdgcn_s_sleep(2);
+      if (wall_clock64() - t0 > kWaitTicks) {
+        ok = 0;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_ready = ok;
+  }
+  __syncthreads();
+  bool ok = s_ready != 0;
+  uint32_t bad = 0;
+  if (ok) {
+    Grid<GangCtrl> g = make_grid(bc, nb, rank);
+    ok = gang_build_csr(j, reinterpret_cast<int32_t*>(sc), reinterpret_cast<uint32_t*>(sc + pv_bytes + acc_bytes),
+                        g, nb, rank, &bad);
+  }
+  if (ok && bad == 0) {
+    const LoopArgs a = gang_args(j.n, j.row_ptr, j.col, j.accepting0, sc, res, ea.flags);
+    if (nb > 1 && !a.sync_sweeps && a.par_bit) map_body_gang_async(a, mcx, nb, rank);
+    else map_body_gang_sync(a, mcx, nb, rank);
+  }
+  // Leave the job: release this block's writes, then report (ranks > 0) or
+  // wait for the others and publish the result (rank 0).
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (rank != 0) {
+      __hip_atomic_fetch_add(&bc->dirty, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      int waited = 1;
+      const uint64_t t0 = wall_clock64();
+      while (ld_agent(&bc->dirty) != (uint32_t)(nb - 1)) {
+        __builtin_amdgcn_s_sleep(2);
+        if (wall_clock64() - t0 > kWaitTicks) {
+          waited = 0;
+          break;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const int32_t* d = reinterpret_cast<const int32_t*>(res);
+      int32_t r[8];
+      for (int i = 0; i < 8; ++i) r[i] = __hip_atomic_load(d + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const bool broken = !ok || !waited || ld_agent((const uint32_t*)&bc->abort) ||
+                          ld_agent((const uint32_t*)&mcx->abort);
+      if (broken || bad) {
+        for (int i = 0; i < 8; ++i) r[i] = 0;
+        r[3] = broken ? MAP_EDEVICE : MAP_ERANGE_DEV;
+      }
+      int32_t* h = reinterpret_cast<int32_t*>(ea.hres + slot);
+      for (int i = 0; i < 8; ++i)
+        if (i != 3) __hip_atomic_store(h + i, r[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+      __hip_atomic_store(h + 3, r[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kBlock) map_engine_kernel(EngineArgs ea) {
+  __shared__ int32_t s_slot, s_rank, s_quit;
+  __shared__ unsigned long long s_start;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const unsigned long long t =
+          __hip_atomic_fetch_add(&ea.dev->head, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int quit = 0;
+      uint64_t t0 = wall_clock64();
+      unsigned long long seen = ~0ull;
+      for (;;) {
+        const unsigned long long mir = __hip_atomic_load(&ea.dev->mirror, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t < mir) break;
+        if (ld_agent(&ea.dev->quit)) {
+          quit = 1;
+          break;
+        }
+        if (mir != seen) {  // progress: restart the idle clock
+          seen = mir;
+          t0 = wall_clock64();
+        }
+        if (t == mir) {
+          // This block holds the first unpublished ticket: it polls the host.
+          unsigned long long tail = __hip_atomic_load(&ea.sh->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          if (tail == mir && __hip_atomic_load(&ea.sh->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
+            // The host publishes before it stops: read the count once more.
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+            tail = __hip_atomic_load(&ea.sh->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (tail == mir) {
+              st_agent(&ea.dev->quit, 1u);
+              quit = 1;
+              break;
+            }
+          }
+          if (tail > mir) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+            __hip_atomic_store(&ea.dev->mirror, tail, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            continue;
+          }
+        }
+        if (wall_clock64() - t0 > ea.idle_ticks) {
+          st_agent(&ea.dev->quit, 1u);
+          __hip_atomic_store(&ea.sh->expired, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          quit = 1;
+          break;
+        }
+        if (t == mir) __builtin_amdgcn_s_sleep(1);
+        else __builtin_amdgcn_s_sleep(8);
+      }
+      s_quit = quit;
+      if (!quit) {
+        // Acquire the host's writes of the ticket, its job and the job's device
+        // buffers (filled by copies the host waited for before publishing).
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+        const unsigned long long e = __hip_atomic_load(ea.ring + (t % (unsigned long long)ea.ring_cap),
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        s_slot = (int32_t)(e >> 32);
+        s_rank = (int32_t)(e & 0xffffffffu);
+        s_start = t - (e & 0xffffffffu);
+      }
+    }
+    __syncthreads();
+    const int quit = s_quit, slot = s_slot, rank = s_rank;
+    const unsigned long long start = s_start;
+    __syncthreads();
+    if (quit) break;
+    if (slot >= 0 && slot < ea.slots) engine_job(ea, slot, rank, start);
   }
 }
 
@@ -1325,7 +1688,52 @@ int batch_device_info(int* cus, int* per_cu) {
   return MAP_OK;
 }
 
+int engine_device_info(int* cus, int* per_cu, int* wall_khz) {
+  static std::mutex mu;
+  static int cache_cus[64], cache_per[64], cache_khz[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return MAP_EDEVICE;
+  std::lock_guard<std::mutex> lock(mu);
+  if (cache_cus[dev] == 0) {
+    int c = 0, nb = 0, khz = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return MAP_EDEVICE;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return MAP_EDEVICE;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(map_engine_kernel), kBlock,
+                                                     0) != hipSuccess)
+      return MAP_EDEVICE;
+    if (c <= 0 || nb <= 0 || khz <= 0) return MAP_EDEVICE;
+    cache_cus[dev] = c;
+    cache_per[dev] = nb;
+    cache_khz[dev] = khz;
+  }
+  *cus = cache_cus[dev];
+  *per_cu = cache_per[dev];
+  *wall_khz = cache_khz[dev];
+  return MAP_OK;
+}
+
+constexpr int32_t kEngineRing = 1 << 17;  // ticket ring entries (1 MiB of host memory)
+
 }  // namespace
+
+// Host state of a serving engine (one per map_engine_create).
+struct map_engine {
+  hipStream_t stream;
+  hipEvent_t exited;             // recorded after the engine launch
+  int grid;                      // workgroups of the launch
+  int32_t slots;
+  char* host;                    // fine-grained host block: shared line, ring, jobs, results
+  EngineShared* sh;
+  unsigned long long* ring;
+  map_job* jobs;
+  map_result* res;
+  char* dmem;                    // device state
+  std::vector<int32_t> free_slots;
+  std::vector<unsigned long long> start;  // first ticket of the job in each busy slot
+  std::vector<uint8_t> busy;
+  unsigned long long tail;       // tickets published
+  bool stopped;
+};
 
 extern "C" {
 
@@ -1461,6 +1869,221 @@ int map_detect_batch(int32_t count, const map_graph_desc* graphs, const int32_t*
   return MAP_OK;
 }
 
+size_t map_job_scratch_bytes(int32_t n, int64_t m) {
+  if (!sizes_ok(n, m)) return 0;
+  return align256((size_t)n * 4) + align256((size_t)n) + (size_t)kMaxGang * 4;
+}
+
+static void engine_free(map_engine* e) {
+  if (e->dmem) (void)hipFree(e->dmem);
+  if (e->host) (void)hipHostFree(e->host);
+  if (e->exited) (void)hipEventDestroy(e->exited);
+  delete e;
+}
+
+int map_engine_create(int32_t max_jobs, int32_t workgroups, double idle_seconds, uint32_t flags, void* stream,
+                      map_engine** out) {
+  if (!out) return MAP_EINVAL;
+  *out = nullptr;
+  if (flags & ~kAllFlags) return MAP_EINVAL;
+  if (max_jobs < 1 || max_jobs > (1 << 16) || workgroups < 0 || !(idle_seconds > 0.0) || idle_seconds > 86400.0)
+    return MAP_ERANGE;
+  int cus = 0, per_cu = 0, khz = 0;
+  int rc = engine_device_info(&cus, &per_cu, &khz);
+  if (rc) return rc;
+  const int full = cus * per_cu;
+  // By default one compute unit per 32 is left to other work (copy kernels of
+  // the runtime, the caller's own launches) while the engine runs.
+  const int grid = workgroups > 0 ? std::min(workgroups, full) : std::max(1, full - cus / 32);
+  map_engine* e = new map_engine();
+  e->stream = reinterpret_cast<hipStream_t>(stream);
+  e->grid = grid;
+  e->slots = max_jobs;
+  const size_t off_ring = sizeof(EngineShared);
+  const size_t off_jobs = off_ring + (size_t)kEngineRing * 8;
+  const size_t off_res = off_jobs + align256((size_t)max_jobs * sizeof(map_job));
+  const size_t host_bytes = off_res + (size_t)max_jobs * sizeof(map_result);
+  void* h = nullptr;
+  if (hipHostMalloc(&h, host_bytes, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess || !h) {
+    delete e;
+    return MAP_EDEVICE;
+  }
+  e->host = static_cast<char*>(h);
+  std::memset(e->host, 0, host_bytes);
+  e->sh = reinterpret_cast<EngineShared*>(e->host);
+  e->ring = reinterpret_cast<unsigned long long*>(e->host + off_ring);
+  e->jobs = reinterpret_cast<map_job*>(e->host + off_jobs);
+  e->res = reinterpret_cast<map_result*>(e->host + off_res);
+  void* hd = nullptr;
+  if (hipHostGetDevicePointer(&hd, h, 0) != hipSuccess || !hd) {
+    engine_free(e);
+    return MAP_EDEVICE;
+  }
+  char* hdev = static_cast<char*>(hd);
+  const size_t off_b = align256(sizeof(EngineDev));
+  const size_t off_m = off_b + (size_t)max_jobs * kGangCtrlBytes;
+  const size_t off_d = off_m + (size_t)max_jobs * kGangCtrlBytes;
+  const size_t off_r = off_d + align256((size_t)max_jobs * sizeof(map_result));
+  const size_t dev_bytes = off_r + align256((size_t)max_jobs * 8);
+  void* dm = nullptr;
+  if (hipMalloc(&dm, dev_bytes) != hipSuccess || !dm) {
+    engine_free(e);
+    return MAP_EDEVICE;
+  }
+  e->dmem = static_cast<char*>(dm);
+  if (hipEventCreateWithFlags(&e->exited, hipEventDisableTiming) != hipSuccess) {
+    e->exited = nullptr;
+    engine_free(e);
+    return MAP_EDEVICE;
+  }
+  e->free_slots.reserve(max_jobs);
+  for (int32_t i = max_jobs - 1; i >= 0; --i) e->free_slots.push_back(i);
+  e->start.assign(max_jobs, 0ull);
+  e->busy.assign(max_jobs, 0);
+  e->tail = 0;
+  e->stopped = false;
+
+  EngineArgs ea;
+  ea.sh = reinterpret_cast<EngineShared*>(hdev);
+  ea.ring = reinterpret_cast<const unsigned long long*>(hdev + off_ring);
+  ea.jobs = reinterpret_cast<const map_job*>(hdev + off_jobs);
+  ea.hres = reinterpret_cast<map_result*>(hdev + off_res);
+  ea.dev = reinterpret_cast<EngineDev*>(e->dmem);
+  ea.bctrl = reinterpret_cast<GangCtrl*>(e->dmem + off_b);
+  ea.mctrl = reinterpret_cast<GangCtrl*>(e->dmem + off_m);
+  ea.dres = reinterpret_cast<map_result*>(e->dmem + off_d);
+  ea.ready = reinterpret_cast<unsigned long long*>(e->dmem + off_r);
+  ea.ring_cap = kEngineRing;
+  ea.slots = max_jobs;
+  ea.idle_ticks = (uint64_t)(idle_seconds * (double)khz * 1000.0);
+  ea.flags = flags;
+  hipLaunchKernelGGL(fill_u32, dim3(grid_for((int64_t)(dev_bytes / 4), 256)), dim3(256), 0, e->stream,
+                     reinterpret_cast<uint32_t*>(e->dmem), (int64_t)(dev_bytes / 4), 0u);
+  void* args[] = {&ea};
+  if (hipGetLastError() != hipSuccess ||
+      hipLaunchCooperativeKernel(reinterpret_cast<const void*>(map_engine_kernel), dim3(grid), dim3(kBlock), args, 0,
+                                 e->stream) != hipSuccess ||
+      hipEventRecord(e->exited, e->stream) != hipSuccess) {
+    // Nothing was launched, or the launch failed: no kernel can be using the memory.
+    (void)hipStreamSynchronize(e->stream);
+    engine_free(e);
+    return MAP_EDEVICE;
+  }
+  *out = e;
+  return MAP_OK;
+}
+
+int map_engine_workgroups(const map_engine* e) { return e ? e->grid : 0; }
+
+// Device address through which the engine reads a job input: device memory
+// as is, pinned host memory through its device mapping; anything else (pageable
+// host memory, unknown pointers) is rejected so the kernel never touches it.
+static int engine_input(const void* p, const void** out) {
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return MAP_EINVAL;
+  }
+  if (at.type == hipMemoryTypeDevice) {
+    *out = p;
+    return MAP_OK;
+  }
+  if (at.type == hipMemoryTypeHost) {
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, const_cast<void*>(p), 0) != hipSuccess || !d) {
+      (void)hipGetLastError();
+      return MAP_EINVAL;
+    }
+    *out = d;
+    return MAP_OK;
+  }
+  return MAP_EINVAL;
+}
+
+static bool engine_output(const void* p) {
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice;
+}
+
+int map_engine_submit(map_engine* e, const map_job* job, int32_t* slot) {
+  if (!e || !job || !slot) return MAP_EINVAL;
+  if (e->stopped) return MAP_EINVAL;
+  if (__atomic_load_n(&e->sh->expired, __ATOMIC_ACQUIRE)) return MAP_EDEVICE;
+  if (!sizes_ok(job->n, job->m)) return MAP_ERANGE;
+  if (!job->row_ptr || !job->accepting0 || !job->scratch) return MAP_EINVAL;
+  if (job->m > 0 && (!job->src || !job->dst || !job->col)) return MAP_EINVAL;
+  if (reinterpret_cast<uintptr_t>(job->scratch) & 255) return MAP_EINVAL;
+  map_job jj = *job;
+  if (engine_input(job->accepting0, reinterpret_cast<const void**>(&jj.accepting0)) ||
+      !engine_output(job->row_ptr) || !engine_output(job->scratch))
+    return MAP_EINVAL;
+  if (job->m > 0 && (engine_input(job->src, reinterpret_cast<const void**>(&jj.src)) ||
+                     engine_input(job->dst, reinterpret_cast<const void**>(&jj.dst)) || !engine_output(job->col)))
+    return MAP_EINVAL;
+  const int32_t gang = std::max(1, std::min(job->gang, std::min(kMaxGang, e->grid)));
+  if (e->free_slots.empty()) return MAP_EBUSY;
+  // The new tickets reuse ring entries of tickets [tail + gang - ring, ...),
+  // which must all have been taken: every ticket below the first one of the
+  // oldest unfinished job has been.
+  unsigned long long oldest = e->tail;
+  for (int32_t i = 0; i < e->slots; ++i)
+    if (e->busy[i] && e->start[i] < oldest) oldest = e->start[i];
+  if (e->tail + (unsigned long long)gang > oldest + (unsigned long long)kEngineRing) return MAP_EBUSY;
+  const int32_t s = e->free_slots.back();
+  e->free_slots.pop_back();
+  jj.gang = gang;
+  e->jobs[s] = jj;
+  map_result r0;
+  std::memset(&r0, 0, sizeof(r0));
+  r0.status = MAP_PENDING;
+  e->res[s] = r0;
+  for (int32_t r = 0; r < gang; ++r)
+    e->ring[(e->tail + (unsigned long long)r) % kEngineRing] = ((unsigned long long)s << 32) | (unsigned)r;
+  e->start[s] = e->tail;
+  e->busy[s] = 1;
+  e->tail += (unsigned long long)gang;
+  __atomic_store_n(&e->sh->tail, e->tail, __ATOMIC_RELEASE);
+  *slot = s;
+  return MAP_OK;
+}
+
+int map_engine_poll(map_engine* e, int32_t slot, map_result* out) {
+  if (!e || slot < 0 || slot >= e->slots || !e->busy[slot]) return MAP_EINVAL;
+  const int32_t st = __atomic_load_n(&e->res[slot].status, __ATOMIC_ACQUIRE);
+  if (st == MAP_PENDING) {
+    // A job still pending after the engine exited (idle bound) never completes.
+    if (hipEventQuery(e->exited) != hipSuccess) return MAP_PENDING;
+    if (__atomic_load_n(&e->res[slot].status, __ATOMIC_ACQUIRE) == MAP_PENDING) {
+      e->busy[slot] = 0;
+      e->free_slots.push_back(slot);
+      return MAP_EDEVICE;
+    }
+  }
+  if (out) std::memcpy(out, &e->res[slot], sizeof(map_result));
+  e->busy[slot] = 0;
+  e->free_slots.push_back(slot);
+  return MAP_OK;
+}
+
+int map_engine_stop(map_engine* e) {
+  if (!e) return MAP_EINVAL;
+  __atomic_store_n(&e->sh->stop, 1u, __ATOMIC_RELEASE);
+  e->stopped = true;
+  return MAP_OK;
+}
+
+int map_engine_destroy(map_engine* e) {
+  if (!e) return MAP_EINVAL;
+  map_engine_stop(e);
+  const int rc = hipEventSynchronize(e->exited) == hipSuccess ? MAP_OK : MAP_EDEVICE;
+  engine_free(e);
+  return rc;
+}
+
 const char* map_strerror(int status) {
   switch (status) {
     case MAP_OK: return "ok";
@@ -1470,6 +2093,8 @@ const char* map_strerror(int status) {
     case MAP_EDEVICE: return "HIP runtime error or device-side barrier timeout";
     case MAP_ENOTCONVERGED: return "iteration or sweep cap reached";
     case MAP_ERANGE_DEV: return "edge endpoint outside 1..n";
+    case MAP_EBUSY: return "engine has no free job slot or ticket space; poll finished jobs first";
+    case MAP_PENDING: return "job not finished yet";
     default: return "unknown status";
   }
 }

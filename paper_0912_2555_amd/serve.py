@@ -1,54 +1,121 @@
 """Serving MAP queries with continuous batching on one GPU.
 
-A query is one graph (edge list + accepting flags).  The server:
+A query is one graph: an edge list and accepting flags in pinned host memory
+(a receive buffer; other host arrays are pinned on arrival).  The server keeps
+one ``map_engine`` running on the device for its whole life and:
 
-* admits a query when its device footprint fits the HBM budget, uploads its
-  edges from pinned memory and builds its CSR on an upload stream; CSR and
-  value state stay resident until the query completes;
-* whenever fewer than ``max_inflight`` batches are on the device, launches one
-  ``map_detect_batch`` over every admitted query whose CSR is ready, on its own
-  stream, so queries that arrive while others run join the next launch and
-  their work overlaps with the batch already on the device (workgroups of the
-  new launch start as those of the older one retire);
-* frees a query's memory when its batch completes and records its latency
-  (arrival to result).
+* admits a query when its device footprint (CSR and scratch) fits the HBM
+  budget: the budget is one arena allocated up front and carved per query by
+  a first-fit allocator, so nothing is allocated while the engine runs;
+* posts the admitted query to the running engine at once: free workgroups
+  pick it up while the engine keeps working on earlier queries, read its edge
+  list and flags straight from pinned host memory, build its CSR into the
+  arena block and run the MAP loop (no copy or launch runs beside the engine);
+* frees the arena block when the engine reports the query finished, and
+  records its latency (arrival to result).
 
 All computation runs in the library's HIP kernels; this module only
-schedules, allocates and copies.
+schedules, allocates and pins.
 """
 from __future__ import annotations
 
+import bisect
 import collections
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 import torch
 
 import paper_0912_2555_amd as mc
 
+_ALIGN = 256
+
+
+def _al(x: int) -> int:
+    return (x + _ALIGN - 1) & ~(_ALIGN - 1)
+
+
+def _layout(n: int, m: int):
+    """Byte offsets of a query's device buffers inside its arena block, and the block size."""
+    off, out = 0, {}
+    for name, nbytes in (("row_ptr", 4 * (n + 1)), ("col", 4 * max(m, 1)),
+                         ("scratch", mc.map_job_scratch_bytes(n, m))):
+        out[name] = (off, nbytes)
+        off += _al(nbytes)
+    return out, off
+
 
 def footprint(n: int, m: int) -> int:
-    """Device bytes a query holds while admitted (CSR, flags, edge staging, scratch)."""
-    return 4 * (n + 1) + 4 * max(m, 1) + n + 8 * max(m, 1) + 5 * n + 2048
+    """Device bytes a query holds while admitted (CSR and scratch)."""
+    return _layout(n, m)[1]
+
+
+class Arena:
+    """First-fit allocator of byte ranges in [0, size), with coalescing frees."""
+
+    def __init__(self, size: int):
+        self.size = size
+        self.free_off = [0]          # sorted offsets of free ranges
+        self.free_len = {0: size}
+
+    def alloc(self, nbytes: int):
+        nbytes = _al(nbytes)
+        for off in self.free_off:
+            ln = self.free_len[off]
+            if ln >= nbytes:
+                i = bisect.bisect_left(self.free_off, off)
+                del self.free_off[i]
+                del self.free_len[off]
+                if ln > nbytes:
+                    bisect.insort(self.free_off, off + nbytes)
+                    self.free_len[off + nbytes] = ln - nbytes
+                return off
+        return None
+
+    def free(self, off: int, nbytes: int):
+        nbytes = _al(nbytes)
+        i = bisect.bisect_left(self.free_off, off)
+        # merge with the next range
+        if i < len(self.free_off) and self.free_off[i] == off + nbytes:
+            nbytes += self.free_len.pop(self.free_off[i])
+            del self.free_off[i]
+        # merge with the previous range
+        if i > 0 and self.free_off[i - 1] + self.free_len[self.free_off[i - 1]] == off:
+            self.free_len[self.free_off[i - 1]] += nbytes
+            return
+        self.free_off.insert(i, off)
+        self.free_len[off] = nbytes
+
+    def free_bytes(self) -> int:
+        return sum(self.free_len.values())
+
+
+def _pinned(x, dtype):
+    """x as a pinned host tensor (a copy unless it already is one)."""
+    if isinstance(x, torch.Tensor) and x.is_pinned():
+        return x
+    t = x if isinstance(x, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(x, dtype=dtype))
+    return t.pin_memory()
 
 
 @dataclass
 class Query:
     qid: int
     n: int
-    src: np.ndarray
-    dst: np.ndarray
-    acc: np.ndarray
-    arrival: float = 0.0          # seconds on the server clock
+    src: object                  # int32[m] edge sources (pinned host tensor; other arrays are pinned on arrival)
+    dst: object                  # int32[m]
+    acc: object                  # uint8[n]
+    arrival: float = 0.0         # seconds on the server clock
     admitted: float = -1.0
+    started: float = -1.0        # posted to the engine
     done: float = -1.0
     result: mc.Result | None = None
-    # device state
-    csr: mc.Csr | None = None
-    acc_dev: torch.Tensor | None = None
-    ready: torch.cuda.Event | None = None
+    # server state
+    off: int = -1
     nbytes: int = 0
+    bufs: dict | None = None
+    slot: int = -1
 
     @property
     def m(self) -> int:
@@ -59,111 +126,93 @@ class Query:
         return self.done - self.arrival
 
 
-@dataclass
-class _InFlight:
-    queries: list
-    batch: mc.Batch
-    stream: torch.cuda.Stream
-    event: torch.cuda.Event
-
-
 class Server:
-    def __init__(self, hbm_budget: int = 32 << 30, max_inflight: int = 2, gang_policy=None, device="cuda"):
-        self.budget = hbm_budget
-        self.used = 0
-        self.max_inflight = max_inflight
-        self.gang_policy = gang_policy      # callable(list of n, list of m) -> gang sizes, or None
+    """Continuous-batching MAP server on one running map_engine."""
+
+    def __init__(self, hbm_budget: int = 32 << 30, gang_policy=None, max_jobs: int = 1024, workgroups: int = 0,
+                 idle_seconds: float = 60.0, device="cuda"):
         self.device = torch.device(device)
-        self.upload = torch.cuda.Stream(device=self.device)
-        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(max_inflight)]
-        self.free_streams = collections.deque(self.streams)
+        self.budget = hbm_budget
+        self.gang_policy = gang_policy      # callable(list of n, list of m) -> gang sizes, or None (1 each)
+        self.arena_mem = torch.empty(hbm_budget, dtype=torch.uint8, device=self.device)
+        self.arena = Arena(hbm_budget)
+        torch.cuda.synchronize(self.device)
+        self.engine = mc.Engine(max_jobs=max_jobs, workgroups=workgroups, idle_seconds=idle_seconds,
+                                device=self.device)
         self.waiting: collections.deque = collections.deque()   # arrived, not admitted
-        self.admitted: list = []                                 # admitted, not launched
-        self.inflight: list = []
+        self.admitted: collections.deque = collections.deque()  # admitted, not yet taken by the engine
+        self.running: dict = {}                                  # slot -> query
         self.finished: list = []
-        self.build_ws = None
         self.t0 = time.perf_counter()
-        self.launches = 0
+        self.submitted = 0
+        self.max_running = 0                                     # most queries on the engine at once
 
     def now(self) -> float:
         return time.perf_counter() - self.t0
 
+    def used(self) -> int:
+        return self.budget - self.arena.free_bytes()
+
     # ------------------------------------------------------------ admission
     def arrive(self, q: Query):
+        if footprint(q.n, q.m) > self.budget:
+            raise ValueError(f"query {q.qid} needs {footprint(q.n, q.m)} bytes, more than the whole budget")
+        q.src, q.dst, q.acc = _pinned(q.src, np.int32), _pinned(q.dst, np.int32), _pinned(q.acc, np.uint8)
         q.arrival = self.now() if q.arrival <= 0 else q.arrival
         self.waiting.append(q)
 
     def _admit(self):
         while self.waiting:
             q = self.waiting[0]
-            need = footprint(q.n, q.m)
-            if need > self.budget:
-                raise ValueError(f"query {q.qid} needs {need} bytes, more than the whole budget")
-            if self.used + need > self.budget:
+            lay, need = _layout(q.n, q.m)
+            off = self.arena.alloc(need)
+            if off is None:
                 return
             self.waiting.popleft()
-            self.used += need
-            q.nbytes = need
-            q.admitted = self.now()
-            with torch.cuda.stream(self.upload):
-                src = torch.from_numpy(q.src).pin_memory().to(self.device, non_blocking=True)
-                dst = torch.from_numpy(q.dst).pin_memory().to(self.device, non_blocking=True)
-                q.acc_dev = torch.from_numpy(q.acc).pin_memory().to(self.device, non_blocking=True)
-                ws_need = mc.map_workspace_bytes(q.n, q.m)
-                if self.build_ws is None or self.build_ws.numel() < ws_need:
-                    self.build_ws = torch.empty(ws_need, dtype=torch.uint8, device=self.device)
-                q.csr = mc.build_csr(q.n, src, dst, transposed=False, ws=self.build_ws, stream=self.upload,
-                                     device=self.device)
-                q.ready = torch.cuda.Event()
-                q.ready.record(self.upload)
+            q.off, q.nbytes, q.admitted = off, need, self.now()
+            b = {k: self.arena_mem[off + o:off + o + ln] for k, (o, ln) in lay.items()}
+            b["row_ptr"] = b["row_ptr"].view(torch.int32)
+            b["col"] = b["col"].view(torch.int32)
+            q.bufs = b
             self.admitted.append(q)
 
-    # ------------------------------------------------------------- launching
-    def _launch(self):
-        if not self.free_streams:
+    # ------------------------------------------------------------ submission
+    def _submit(self):
+        if not self.admitted:
             return
-        ready = [q for q in self.admitted if q.ready.query()]
-        if not ready:
-            return
-        ready.sort(key=lambda q: -q.m)                           # largest first
-        self.admitted = [q for q in self.admitted if q not in ready]
-        stream = self.free_streams.popleft()
-        gang = self.gang_policy([q.n for q in ready], [q.m for q in ready]) if self.gang_policy else None
-        with torch.cuda.stream(stream):
-            # descriptors, results and workspace are allocated and uploaded on
-            # the launch stream, so the launch is ordered after them
-            b = mc.Batch([q.csr for q in ready], [q.acc_dev for q in ready], gang=gang, device=self.device)
-            b.launch(stream=stream)
-            ev = torch.cuda.Event()
-            ev.record(stream)
-        self.launches += 1
-        self.inflight.append(_InFlight(ready, b, stream, ev))
+        batch = list(self.admitted)
+        gangs = self.gang_policy([q.n for q in batch], [q.m for q in batch]) if self.gang_policy else None
+        for i, q in enumerate(batch):
+            b, m = q.bufs, q.m
+            slot = self.engine.submit(q.n, q.src if m else None, q.dst if m else None, b["row_ptr"],
+                                      b["col"], q.acc, b["scratch"], gang=gangs[i] if gangs else 1, tag=q.qid)
+            if slot is None:                      # engine full: retry on the next poll
+                return
+            self.admitted.popleft()
+            q.slot, q.started = slot, self.now()
+            self.running[slot] = q
+            self.submitted += 1
+            self.max_running = max(self.max_running, len(self.running))
 
     # ------------------------------------------------------------ completion
     def _complete(self):
-        still = []
-        for f in self.inflight:
-            if f.event.query():
-                t = self.now()
-                for q, r in zip(f.queries, f.batch.read()):
-                    q.result = r
-                    q.done = t
-                    self.used -= q.nbytes
-                    q.csr = None
-                    q.acc_dev = None
-                    self.finished.append(q)
-                self.free_streams.append(f.stream)
-            else:
-                still.append(f)
-        self.inflight = still
+        for slot in list(self.running):
+            r = self.engine.poll(slot)
+            if r is None:
+                continue
+            q = self.running.pop(slot)
+            q.result, q.done = r, self.now()
+            self.arena.free(q.off, q.nbytes)
+            q.bufs = None
+            self.finished.append(q)
 
     def poll(self):
         self._complete()
         self._admit()
-        self._launch()
+        self._submit()
 
     def idle(self) -> bool:
-        return not (self.waiting or self.admitted or self.inflight)
+        return not (self.waiting or self.admitted or self.running)
 
     def drain(self, timeout: float = 600.0):
         t = time.perf_counter()
@@ -171,7 +220,22 @@ class Server:
             self.poll()
             if time.perf_counter() - t > timeout:
                 raise TimeoutError("server did not drain")
-            time.sleep(50e-6)
+            time.sleep(20e-6)
+
+    def close(self):
+        self.engine.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _stats(queries, span):
+    lat = np.array([q.latency for q in queries])
+    return {"graphs_per_s": len(queries) / span, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3), "span_s": span}
 
 
 def run_stream(queries, qps: float, server: Server, gaps=None):
@@ -187,12 +251,10 @@ def run_stream(queries, qps: float, server: Server, gaps=None):
             server.arrive(queries[i])
             i += 1
         server.poll()
-        time.sleep(20e-6)
-    span = server.now() - start
-    lat = np.array([q.latency for q in queries])
-    return {"graphs_per_s": len(queries) / span, "p50_ms": float(np.percentile(lat, 50) * 1e3),
-            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
-            "span_s": span, "launches": server.launches}
+        time.sleep(10e-6)
+    out = _stats(queries, server.now() - start)
+    out["jobs"] = server.submitted
+    return out
 
 
 def run_serial(queries, qps: float, gaps=None, device="cuda"):
@@ -207,8 +269,11 @@ def run_serial(queries, qps: float, gaps=None, device="cuda"):
         now = time.perf_counter() - t0
         if now < a:
             time.sleep(a - now)
-        csr = mc.build_csr(q.n, q.src, q.dst, transposed=False, device=dev)
-        out = mc.detect(csr, q.acc)
+        src = _pinned(q.src, np.int32).to(dev, non_blocking=True)
+        dst = _pinned(q.dst, np.int32).to(dev, non_blocking=True)
+        acc = _pinned(q.acc, np.uint8).to(dev, non_blocking=True)
+        csr = mc.build_csr(q.n, src, dst, transposed=False, device=dev)
+        out = mc.detect(csr, acc)
         results.append(out.result)
         lat.append(time.perf_counter() - t0 - a)
     span = time.perf_counter() - t0

@@ -37,7 +37,9 @@ def declared_functions():
 
 def test_exports_every_declared_symbol(lib):
     names = declared_functions()
-    assert names == ["map_batch_workspace_bytes", "map_build_csr", "map_detect", "map_detect_batch", "map_propagate",
+    assert names == ["map_batch_workspace_bytes", "map_build_csr", "map_detect", "map_detect_batch",
+                     "map_engine_create", "map_engine_destroy", "map_engine_poll", "map_engine_stop",
+                     "map_engine_submit", "map_engine_workgroups", "map_job_scratch_bytes", "map_propagate",
                      "map_strerror", "map_workspace_bytes"]
     for name in names:
         assert hasattr(lib, name), name
@@ -49,8 +51,8 @@ def test_header_compiles_as_c():
     with tempfile.TemporaryDirectory() as d:
         src = os.path.join(d, "t.c")
         with open(src, "w") as f:
-            f.write('#include "mapcheck.h"\nint main(void){ map_result r; (void)r; '
-                    'return (int)sizeof(map_result) - 32; }\n')
+            f.write('#include "mapcheck.h"\nint main(void){ map_result r; map_job j; (void)r; (void)j; '
+                    'return (int)sizeof(map_result) - 32 + (int)sizeof(map_job) - 72; }\n')
         subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
                                "-o", os.path.join(d, "t"), src])
         assert subprocess.call([os.path.join(d, "t")]) == 0
@@ -94,3 +96,35 @@ def test_strerror(lib):
     for code in range(-6, 1):
         assert lib.map_strerror(code).decode()
     assert lib.map_strerror(99).decode() == "unknown status"
+
+
+def test_engine_host_side_errors_without_device(lib):
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.map_job_scratch_bytes.argtypes = [i32, i64]
+    lib.map_job_scratch_bytes.restype = ctypes.c_size_t
+    lib.map_engine_create.argtypes = [i32, i32, ctypes.c_double, ctypes.c_uint32, vp, ctypes.POINTER(vp)]
+    lib.map_engine_submit.argtypes = [vp, vp, ctypes.POINTER(i32)]
+    lib.map_engine_poll.argtypes = [vp, i32, vp]
+    lib.map_engine_stop.argtypes = [vp]
+    lib.map_engine_destroy.argtypes = [vp]
+    lib.map_engine_workgroups.argtypes = [vp]
+    # scratch: packed values (4n) + flags (n), each 256-aligned, + per-rank scan partials
+    assert lib.map_job_scratch_bytes(1000, 5000) == 4096 + 1024 + 1024
+    assert lib.map_job_scratch_bytes(0, 5) == 0
+    assert lib.map_job_scratch_bytes(10, -1) == 0
+    h = vp()
+    assert lib.map_engine_create(16, 0, 1.0, 0, None, None) == MAP_EINVAL
+    assert lib.map_engine_create(16, 0, 1.0, 0x100, None, ctypes.byref(h)) == MAP_EINVAL
+    assert lib.map_engine_create(0, 0, 1.0, 0, None, ctypes.byref(h)) == MAP_ERANGE
+    assert lib.map_engine_create(1 << 17, 0, 1.0, 0, None, ctypes.byref(h)) == MAP_ERANGE
+    assert lib.map_engine_create(16, -1, 1.0, 0, None, ctypes.byref(h)) == MAP_ERANGE
+    assert lib.map_engine_create(16, 0, 0.0, 0, None, ctypes.byref(h)) == MAP_ERANGE
+    assert h.value is None
+    slot = i32()
+    assert lib.map_engine_submit(None, None, ctypes.byref(slot)) == MAP_EINVAL
+    assert lib.map_engine_poll(None, 0, None) == MAP_EINVAL
+    assert lib.map_engine_stop(None) == MAP_EINVAL
+    assert lib.map_engine_destroy(None) == MAP_EINVAL
+    assert lib.map_engine_workgroups(None) == 0
+    assert lib.map_strerror(-7).decode().startswith("engine")
+    assert lib.map_strerror(1).decode() == "job not finished yet"

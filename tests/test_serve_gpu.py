@@ -1,5 +1,7 @@
-"""Serving with continuous batching: every query's result is the same alone
-(one map_detect call) and in the mix, and matches the oracle (bit-exact)."""
+"""Serving with continuous batching on the persistent engine: every query's
+result is the same alone (one map_detect call) and in the mix, and matches
+the oracle (bit-exact); queries overlap on the device; admission keeps to
+the HBM budget."""
 import numpy as np
 import pytest
 
@@ -33,16 +35,20 @@ def test_serving_mix_equals_alone(mods):
         csr = mc.build_csr(g.n, g.src, g.dst, transposed=False)
         alone.append(mc.detect(csr, g.acc).result)
     qs = [serve.Query(i, g.n, g.src, g.dst, g.acc) for i, g in enumerate(gs)]
-    srv = serve.Server(hbm_budget=64 << 20, max_inflight=2)       # small budget: admission must queue
-    stats = serve.run_stream(qs, qps=2000.0, server=srv)
-    assert srv.launches >= 2
+    budget = 24 << 20                                            # small: admission must queue
+    assert sum(serve.footprint(g.n, g.m) for g in gs) > budget
+    with serve.Server(hbm_budget=budget, idle_seconds=30.0) as srv:
+        stats = serve.run_stream(qs, qps=2000.0, server=srv)
+        assert srv.max_running >= 2                              # queries overlapped on the engine
+        assert srv.used() == 0
     for q, a, ref in zip(qs, alone, refs):
         r = q.result
         assert r.status == 0, (q.qid, r)
         assert r.verdict == a.verdict == ref.verdict, (q.qid, r.verdict, a.verdict, ref.verdict)
         assert r.accepting_left == a.accepting_left == ref.accepting_left
-        assert q.latency > 0
+        assert q.latency > 0 and q.started >= q.admitted >= q.arrival - 1e-9
     assert stats["p99_ms"] >= stats["p50_ms"] > 0
+    assert stats["jobs"] == len(qs)
 
 
 def test_serving_with_gangs(mods):
@@ -51,9 +57,9 @@ def test_serving_with_gangs(mods):
     gs = _queries()[:10]
     refs = [oracle.map_detect(g, mode="desc") for g in gs]
     qs = [serve.Query(i, g.n, g.src, g.dst, g.acc) for i, g in enumerate(gs)]
-    srv = serve.Server(hbm_budget=1 << 30, max_inflight=2,
-                       gang_policy=lambda ns, ms: autotune.gang_sizes(ns, ms, (1 << 17, True)))
-    serve.run_stream(qs, qps=500.0, server=srv)
+    with serve.Server(hbm_budget=1 << 30, idle_seconds=30.0,
+                      gang_policy=lambda ns, ms: autotune.gang_sizes(ns, ms, (1 << 17, True))) as srv:
+        serve.run_stream(qs, qps=500.0, server=srv)
     for q, ref in zip(qs, refs):
         assert q.result.status == 0 and q.result.verdict == ref.verdict
 
@@ -62,7 +68,6 @@ def test_admission_respects_budget(mods):
     mc, serve = mods
     g = synth.config4(2)
     q = serve.Query(0, g.n, g.src, g.dst, g.acc)
-    srv = serve.Server(hbm_budget=serve.footprint(g.n, g.m) - 1)
-    with pytest.raises(ValueError):
-        srv.arrive(q)
-        srv.poll()
+    with serve.Server(hbm_budget=serve.footprint(g.n, g.m) - 256, idle_seconds=30.0) as srv:
+        with pytest.raises(ValueError):
+            srv.arrive(q)
