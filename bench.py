@@ -230,7 +230,7 @@ def bench_serve(args):
         return [serve.Query(i, g.n, p[0], p[1], p[2]) for i, (g, p) in enumerate(zip(graphs, pinned))]
 
     # serial plain throughput, saturated (back-to-back), on a sample
-    sample = queries()[:min(count, 64)]
+    sample = queries()[:min(count, 200)]
     serve.run_serial(sample[:4], qps=1e9)                      # warm-up
     sat, _ = serve.run_serial(sample, qps=1e9)
     rate = sat["graphs_per_s"]
@@ -238,35 +238,32 @@ def bench_serve(args):
     print(f"[bench] serial saturated {rate:.2f} graphs/s -> offered load {qps:.2f} queries/s", file=sys.stderr,
           flush=True)
 
-    # gang policy: tuned on the sample solved as one batch (before serving)
-    if args.serve_policy == "tune":
-        s_csrs = [mc.build_csr(q.n, q.src, q.dst, transposed=False) for q in sample]
-        s_accs = [q.acc.cuda() for q in sample]
-        order = sorted(range(len(sample)), key=lambda i: -sample[i].m)
-        policy, _ = autotune.tune(lambda gang: mc.Batch([s_csrs[i] for i in order], [s_accs[i] for i in order],
-                                                        gang=gang),
-                                  [sample[i].n for i in order], [sample[i].m for i in order],
-                                  torch.cuda.get_device_name(0), use_cache=False,
-                                  log=lambda x: print(x, file=sys.stderr, flush=True))
-        del s_csrs, s_accs
-    else:
-        policy = autotune.parse_policy(args.serve_policy)
-    gang_policy = (lambda ns, ms: autotune.gang_sizes(ns, ms, policy)) if policy else None
-    torch.cuda.synchronize()
-
     budget = 32 << 30
-    with serve.Server(hbm_budget=budget, gang_policy=gang_policy) as srv:
+    with serve.Server(hbm_budget=budget) as srv:
         warm = queries()[:16]
         serve.run_stream(warm, qps=1e9, server=srv)             # warm-up
+        # gang policy: each candidate serves a sample of the stream, all at once, on this engine
+        if args.serve_policy == "tune":
+            tsample = queries()[:min(count, 200)]
+
+            def trial(pol):
+                srv.gang_policy = (lambda ns, ms: autotune.gang_sizes(ns, ms, pol)) if pol else None
+                return serve.run_stream([serve.Query(q.qid, q.n, q.src, q.dst, q.acc) for q in tsample],
+                                        qps=1e9, server=srv)["span_s"]
+            policy, tuner = autotune.tune_by(trial, log=lambda x: print(x, file=sys.stderr, flush=True))
+        else:
+            policy, tuner = autotune.parse_policy(args.serve_policy), None
+        srv.gang_policy = (lambda ns, ms: autotune.gang_sizes(ns, ms, policy)) if policy else None
+        srv.max_running = 0
         qs = queries()
         st = serve.run_stream(qs, qps=qps, server=srv, gaps=gaps)
+        max_running = srv.max_running
         over = None
         if args.rho_over > 0:
             qo = queries()
             over = serve.run_stream(qo, qps=args.rho_over * rate, server=srv, gaps=gaps)
         qsat = queries()
         sat_engine = serve.run_stream(qsat, qps=1e9, server=srv)  # everything at once: engine capacity
-        max_running = srv.max_running
         workgroups = srv.engine.workgroups
     ser, ser_res = serve.run_serial(queries(), qps=qps, gaps=gaps)
     exact = all(q.result.status == 0 and q.result.verdict == r.verdict and q.result.accepting_left == r.accepting_left
@@ -286,6 +283,7 @@ def bench_serve(args):
         "engine_saturated": rnd(sat_engine),
         "overload": ({"rho": args.rho_over, **rnd(over)} if over else None),
         "max_queries_on_engine": max_running,
+        "tuner_ms": ({k: round(v * 1e3, 2) for k, v in tuner.items()} if tuner else None),
         "exact_vs_serial": exact, "exact_saturated_vs_stream": exact_sat,
     }
     print(json.dumps(out), flush=True)

@@ -26,7 +26,7 @@ RES_ROWS = 4096
 # Upper bound on a gang; the library also clamps to the workgroups of the launch.
 CAP = 256
 CANDIDATES = (None,
-              (1 << 18, False), (1 << 16, False), (1 << 15, False),
+              (1 << 18, False), (1 << 16, False), (1 << 15, False), (1 << 14, False),
               (1 << 18, True), (1 << 16, True), (1 << 15, True), (1 << 14, True))
 
 
@@ -112,3 +112,16 @@ def tune(make_batch, ns, ms, device_name: str, reps: int = 2, use_cache: bool = 
         except OSError:
             pass
     return best_policy, timings
+
+
+def tune_by(run, candidates=CANDIDATES, log=None):
+    """Time run(policy) -> seconds for each candidate policy; return (fastest policy, timings by name)."""
+    timings, best, best_t = {}, None, float("inf")
+    for cand in candidates:
+        t = run(cand)
+        timings[policy_name(cand)] = t
+        if log:
+            log(f"[tune] {policy_name(cand)}: {t * 1e3:.2f} ms")
+        if t < best_t:
+            best, best_t = cand, t
+    return best, timings

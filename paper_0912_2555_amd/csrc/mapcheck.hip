@@ -1058,10 +1058,18 @@ struct alignas(128) EngineDev {  // device memory
   uint32_t pad2[31];
 };
 
+// A job as the engine reads it: the caller's map_job with its inputs resolved
+// to device addresses, and whether the edge list lies in host memory.
+struct EngineJob {
+  map_job j;
+  uint64_t host_edges;
+};
+static_assert(sizeof(EngineJob) % 8 == 0, "jobs are read as 64-bit words");
+
 struct EngineArgs {
   EngineShared* sh;                // device address of the shared host block
   const unsigned long long* ring;  // [ring_cap] host: (slot << 32) | rank
-  const map_job* jobs;             // [slots] host
+  const EngineJob* jobs;           // [slots] host
   map_result* hres;                // [slots] host: status MAP_PENDING until the job is done
   EngineDev* dev;
   GangCtrl* bctrl;                 // [slots] barriers of the CSR build
@@ -1074,7 +1082,6 @@ struct EngineArgs {
   uint32_t flags;
 };
 
-static_assert(sizeof(map_job) % 8 == 0, "map_job is read as 64-bit words");
 
 __device__ uint32_t block_sum_u32(uint32_t x) {
   __shared__ uint32_t s_bs[kWavesPerBlock];
@@ -1121,13 +1128,14 @@ __device__ Grid<C> make_grid(C* c, int nb, int b) {
   return g;
 }
 
-// Calls f(src[e], dst[e]) for the edges e = gt, gt + gs, ... of [0, m).  The
-// arrays may live in host memory, where every load is a bus round trip, so
-// when both are 16-byte aligned they are read four edges at a time with two
-// such loads per array in flight.
+// Calls f(src[e], dst[e]) for the edges e = gt, gt + gs, ... of [0, m), and
+// copies them to copy_src / copy_dst when those are given.  The arrays may
+// live in host memory, where every load is a bus round trip, so when both are
+// 16-byte aligned they are read four edges at a time with two such loads per
+// array in flight.
 template <typename F>
 __device__ __forceinline__ void for_edges(const int32_t* src, const int32_t* dst, int64_t m, int64_t gt,
-                                          int64_t gs, F f) {
+                                          int64_t gs, int32_t* copy_src, int32_t* copy_dst, F f) {
   int64_t e0 = 0;
   if (((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0) {
     const int64_t q = m / 4;
@@ -1136,6 +1144,12 @@ __device__ __forceinline__ void for_edges(const int32_t* src, const int32_t* dst
     int64_t i = gt;
     for (; i + gs < q; i += 2 * gs) {
       const int4 a = s4[i], b = d4[i], c = s4[i + gs], d = d4[i + gs];
+      if (copy_src) {
+        reinterpret_cast<int4*>(copy_src)[i] = a;
+        reinterpret_cast<int4*>(copy_dst)[i] = b;
+        reinterpret_cast<int4*>(copy_src)[i + gs] = c;
+        reinterpret_cast<int4*>(copy_dst)[i + gs] = d;
+      }
       f(a.x, b.x);
       f(a.y, b.y);
       f(a.z, b.z);
@@ -1147,6 +1161,10 @@ __device__ __forceinline__ void for_edges(const int32_t* src, const int32_t* dst
     }
     if (i < q) {
       const int4 a = s4[i], b = d4[i];
+      if (copy_src) {
+        reinterpret_cast<int4*>(copy_src)[i] = a;
+        reinterpret_cast<int4*>(copy_dst)[i] = b;
+      }
       f(a.x, b.x);
       f(a.y, b.y);
       f(a.z, b.z);
@@ -1154,16 +1172,25 @@ __device__ __forceinline__ void for_edges(const int32_t* src, const int32_t* dst
     }
     e0 = q * 4;
   }
-  for (int64_t e = e0 + gt; e < m; e += gs) f(src[e], dst[e]);
+  for (int64_t e = e0 + gt; e < m; e += gs) {
+    const int32_t a = src[e], b = dst[e];
+    if (copy_src) {
+      copy_src[e] = a;
+      copy_dst[e] = b;
+    }
+    f(a, b);
+  }
 }
 
 // Pull CSR of a job's edge list, built by its gang: the same arrays that
 // map_build_csr produces, up to the order of columns inside a row.  cursor is
-// int32[n] and part uint32[nb] of scratch.  Returns false if a gang barrier
-// timed out; *bad = edges with an endpoint outside 1..n (the CSR is then
-// unspecified and the gang stops after the histogram).
-__device__ bool gang_build_csr(const map_job& j, int32_t* cursor, uint32_t* part, Grid<GangCtrl>& g, int nb,
-                               int rank, uint32_t* bad) {
+// int32[n] and part uint32[nb] of scratch.  With stage_src / stage_dst (edge
+// list in host memory) the histogram pass also copies the edges there, so the
+// bus is crossed once and the scatter reads device memory.  Returns false if a
+// gang barrier timed out; *bad = edges with an endpoint outside 1..n (the CSR
+// is then unspecified and the gang stops after the histogram).
+__device__ bool gang_build_csr(const map_job& j, int32_t* cursor, uint32_t* part, int32_t* stage_src,
+                               int32_t* stage_dst, Grid<GangCtrl>& g, int nb, int rank, uint32_t* bad) {
   const int32_t n = j.n;
   const int64_t m = j.m;
   int32_t* rp = j.row_ptr;
@@ -1172,7 +1199,7 @@ __device__ bool gang_build_csr(const map_job& j, int32_t* cursor, uint32_t* part
   if (!grid_sync(g, 0u, nullptr)) return false;
   // Degree histogram: the count of row v (vertex v+1) lands at rp[v+1].
   uint32_t nbad = 0;
-  for_edges(j.src, j.dst, m, gt, gs, [&](int32_t s, int32_t d) {
+  for_edges(j.src, j.dst, m, gt, gs, stage_src, stage_dst, [&](int32_t s, int32_t d) {
     if (s < 1 || s > n || d < 1 || d > n) {
       ++nbad;
       return;
@@ -1207,7 +1234,9 @@ __device__ bool gang_build_csr(const map_job& j, int32_t* cursor, uint32_t* part
   for (int64_t r = gt; r < n; r += gs) cursor[r] = rp[r];
   if (!grid_sync(g, 0u, nullptr)) return false;
   int32_t* col = j.col;
-  for_edges(j.src, j.dst, m, gt, gs, [&](int32_t s, int32_t d) {
+  const int32_t* src = stage_src ? stage_src : j.src;
+  const int32_t* dst = stage_src ? stage_dst : j.dst;
+  for_edges(src, dst, m, gt, gs, nullptr, nullptr, [&](int32_t s, int32_t d) {
     const int32_t pos = __hip_atomic_fetch_add(&cursor[s - 1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     col[pos] = d - 1;
   });
@@ -1218,15 +1247,16 @@ __device__ bool gang_build_csr(const map_job& j, int32_t* cursor, uint32_t* part
 // control blocks before any rank uses them, and publishes the result to host
 // memory after every other rank has left the job.
 __device__ __noinline__ void engine_job(const EngineArgs& ea, int slot, int rank, unsigned long long start) {
-  constexpr int kJobWords = (int)(sizeof(map_job) / 8);
+  constexpr int kJobWords = (int)(sizeof(EngineJob) / 8);
   __shared__ unsigned long long s_job[kJobWords];
   __shared__ int s_ready;
   if (threadIdx.x < kJobWords)
     s_job[threadIdx.x] = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(ea.jobs + slot) + threadIdx.x,
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   __syncthreads();
-  map_job j;
-  memcpy(&j, s_job, sizeof(j));
+  EngineJob ej;
+  memcpy(&ej, s_job, sizeof(ej));
+  const map_job& j = ej.j;
   const int nb = max(1, min(j.gang, min((int)gridDim.x, kMaxGang)));
   GangCtrl* bc = ea.bctrl + slot;
   GangCtrl* mcx = ea.mctrl + slot;
@@ -1268,8 +1298,11 @@ __device__ __noinline__ void engine_job(const EngineArgs& ea, int slot, int rank
   uint32_t bad = 0;
   if (ok) {
     Grid<GangCtrl> g = make_grid(bc, nb, rank);
+    char* stage = sc + pv_bytes + acc_bytes + (size_t)kMaxGang * 4;
+    const size_t edge_bytes = ((size_t)j.m * 4 + 255) & ~(size_t)255;
     ok = gang_build_csr(j, reinterpret_cast<int32_t*>(sc), reinterpret_cast<uint32_t*>(sc + pv_bytes + acc_bytes),
-                        g, nb, rank, &bad);
+                        ej.host_edges ? reinterpret_cast<int32_t*>(stage) : nullptr,
+                        ej.host_edges ? reinterpret_cast<int32_t*>(stage + edge_bytes) : nullptr, g, nb, rank, &bad);
   }
   if (ok && bad == 0) {
     const LoopArgs a = gang_args(j.n, j.row_ptr, j.col, j.accepting0, sc, res, ea.flags);
@@ -1725,7 +1758,7 @@ struct map_engine {
   char* host;                    // fine-grained host block: shared line, ring, jobs, results
   EngineShared* sh;
   unsigned long long* ring;
-  map_job* jobs;
+  EngineJob* jobs;
   map_result* res;
   char* dmem;                    // device state
   std::vector<int32_t> free_slots;
@@ -1871,7 +1904,8 @@ int map_detect_batch(int32_t count, const map_graph_desc* graphs, const int32_t*
 
 size_t map_job_scratch_bytes(int32_t n, int64_t m) {
   if (!sizes_ok(n, m)) return 0;
-  return align256((size_t)n * 4) + align256((size_t)n) + (size_t)kMaxGang * 4;
+  // packed values | working flags | scan partials | staged edge list (src, dst)
+  return align256((size_t)n * 4) + align256((size_t)n) + (size_t)kMaxGang * 4 + 2 * align256((size_t)m * 4);
 }
 
 static void engine_free(map_engine* e) {
@@ -1901,7 +1935,7 @@ int map_engine_create(int32_t max_jobs, int32_t workgroups, double idle_seconds,
   e->slots = max_jobs;
   const size_t off_ring = sizeof(EngineShared);
   const size_t off_jobs = off_ring + (size_t)kEngineRing * 8;
-  const size_t off_res = off_jobs + align256((size_t)max_jobs * sizeof(map_job));
+  const size_t off_res = off_jobs + align256((size_t)max_jobs * sizeof(EngineJob));
   const size_t host_bytes = off_res + (size_t)max_jobs * sizeof(map_result);
   void* h = nullptr;
   if (hipHostMalloc(&h, host_bytes, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess || !h) {
@@ -1912,7 +1946,7 @@ int map_engine_create(int32_t max_jobs, int32_t workgroups, double idle_seconds,
   std::memset(e->host, 0, host_bytes);
   e->sh = reinterpret_cast<EngineShared*>(e->host);
   e->ring = reinterpret_cast<unsigned long long*>(e->host + off_ring);
-  e->jobs = reinterpret_cast<map_job*>(e->host + off_jobs);
+  e->jobs = reinterpret_cast<EngineJob*>(e->host + off_jobs);
   e->res = reinterpret_cast<map_result*>(e->host + off_res);
   void* hd = nullptr;
   if (hipHostGetDevicePointer(&hd, h, 0) != hipSuccess || !hd) {
@@ -1946,7 +1980,7 @@ int map_engine_create(int32_t max_jobs, int32_t workgroups, double idle_seconds,
   EngineArgs ea;
   ea.sh = reinterpret_cast<EngineShared*>(hdev);
   ea.ring = reinterpret_cast<const unsigned long long*>(hdev + off_ring);
-  ea.jobs = reinterpret_cast<const map_job*>(hdev + off_jobs);
+  ea.jobs = reinterpret_cast<const EngineJob*>(hdev + off_jobs);
   ea.hres = reinterpret_cast<map_result*>(hdev + off_res);
   ea.dev = reinterpret_cast<EngineDev*>(e->dmem);
   ea.bctrl = reinterpret_cast<GangCtrl*>(e->dmem + off_b);
@@ -1978,7 +2012,7 @@ int map_engine_workgroups(const map_engine* e) { return e ? e->grid : 0; }
 // Device address through which the engine reads a job input: device memory
 // as is, pinned host memory through its device mapping; anything else (pageable
 // host memory, unknown pointers) is rejected so the kernel never touches it.
-static int engine_input(const void* p, const void** out) {
+static int engine_input(const void* p, const void** out, bool* host = nullptr) {
   hipPointerAttribute_t at;
   if (hipPointerGetAttributes(&at, p) != hipSuccess) {
     (void)hipGetLastError();
@@ -1995,6 +2029,7 @@ static int engine_input(const void* p, const void** out) {
       return MAP_EINVAL;
     }
     *out = d;
+    if (host) *host = true;
     return MAP_OK;
   }
   return MAP_EINVAL;
@@ -2017,13 +2052,19 @@ int map_engine_submit(map_engine* e, const map_job* job, int32_t* slot) {
   if (!job->row_ptr || !job->accepting0 || !job->scratch) return MAP_EINVAL;
   if (job->m > 0 && (!job->src || !job->dst || !job->col)) return MAP_EINVAL;
   if (reinterpret_cast<uintptr_t>(job->scratch) & 255) return MAP_EINVAL;
-  map_job jj = *job;
+  EngineJob ej;
+  std::memset(&ej, 0, sizeof(ej));
+  map_job& jj = ej.j;
+  jj = *job;
+  bool host_src = false, host_dst = false;
   if (engine_input(job->accepting0, reinterpret_cast<const void**>(&jj.accepting0)) ||
       !engine_output(job->row_ptr) || !engine_output(job->scratch))
     return MAP_EINVAL;
-  if (job->m > 0 && (engine_input(job->src, reinterpret_cast<const void**>(&jj.src)) ||
-                     engine_input(job->dst, reinterpret_cast<const void**>(&jj.dst)) || !engine_output(job->col)))
+  if (job->m > 0 && (engine_input(job->src, reinterpret_cast<const void**>(&jj.src), &host_src) ||
+                     engine_input(job->dst, reinterpret_cast<const void**>(&jj.dst), &host_dst) ||
+                     !engine_output(job->col)))
     return MAP_EINVAL;
+  ej.host_edges = (host_src || host_dst) ? 1u : 0u;
   const int32_t gang = std::max(1, std::min(job->gang, std::min(kMaxGang, e->grid)));
   if (e->free_slots.empty()) return MAP_EBUSY;
   // The new tickets reuse ring entries of tickets [tail + gang - ring, ...),
@@ -2036,7 +2077,7 @@ int map_engine_submit(map_engine* e, const map_job* job, int32_t* slot) {
   const int32_t s = e->free_slots.back();
   e->free_slots.pop_back();
   jj.gang = gang;
-  e->jobs[s] = jj;
+  e->jobs[s] = ej;
   map_result r0;
   std::memset(&r0, 0, sizeof(r0));
   r0.status = MAP_PENDING;

@@ -92,8 +92,8 @@ class Arena:
 
 
 def _pinned(x, dtype):
-    """x as a pinned host tensor (a copy unless it already is one)."""
-    if isinstance(x, torch.Tensor) and x.is_pinned():
+    """x as a device or pinned host tensor (a pinned copy of anything else)."""
+    if isinstance(x, torch.Tensor) and (x.is_cuda or x.is_pinned()):
         return x
     t = x if isinstance(x, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(x, dtype=dtype))
     return t.pin_memory()
