@@ -44,7 +44,7 @@ constexpr int kResRowsPerLane = 4;                     // resident mode: rows pe
 constexpr int kResWaveRows = kWave * kResRowsPerLane;  // resident mode: rows per wave
 constexpr int kResEdges = 24576;                        // resident mode: CSR edges per block in LDS
 constexpr int kGatherBatch = 12;                        // resident mode: gathers in flight per lane
-constexpr int kLocalPasses = 2;                         // resident mode: LDS-only passes after a sweep
+constexpr int kLocalPasses = 4;                         // resident mode: LDS-only passes after a sweep
 constexpr int kSortSlots = 1024;                        // resident mode: bitonic sort width (>= 64 * kGatherBatch)
 constexpr int kSortPerLane = kSortSlots / kWave;
 static_assert(kSortSlots >= kWave * kGatherBatch, "sort must cover a gather batch");
@@ -294,7 +294,9 @@ struct WaveRows {
   int64_t rb0, rb1;  // rows of this block
   int64_t r0, r1;  // rows of this wave
   int32_t we0, we1;  // resident: edge range of the wave inside the block's LDS slice
+  int32_t wr;        // resident: [we0, wr) edges to rows of other blocks, [wr, we1) to rows of this block
   bool resident;
+  bool ascending;    // stream: sweep tiles in increasing row order (most edges point to lower rows)
 };
 
 // The block's LDS, at namespace scope so that out-of-line sweep functions
@@ -398,12 +400,48 @@ __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int64_t r0
   return __ballot(changed) != 0;
 }
 
-// Resident mode: one sweep over the wave's rows from its LDS slice.
-// kFirst: the reset sweep (successors send their id if accepting).
-// kLocal: a pass over edges whose target is a row of this block only, reading
-// the block's values from LDS (values move along in-block edges without a
-// round trip to memory).  Otherwise in-block targets are read from LDS and the
-// others gathered from memory.
+// Resident mode: one pass over a range of the wave's staged edges, folding
+// what each edge's successor sends into best[row] with LDS atomic max.
+// kSrc 0: first sweep of an iteration (successors send their id if
+// accepting); 1: successors owned by other blocks, gathered from memory;
+// 2: successors owned by this block, read from the block's LDS values.
+template <int kSrc>
+__device__ __forceinline__ void gather_range(const uint8_t* acc, int32_t e0, int32_t e1, uint32_t* best,
+                                             const LoopArgs& a, uint32_t base, int lane, uint32_t cur) {
+  ResLds& R = g_lds.res;
+  g_u32* pv = (g_u32*)a.pv;
+  const uint32_t n = (uint32_t)a.n, vmask = a.val_mask, pbit = a.par_bit;
+  for (int32_t k0 = e0; k0 < e1; k0 += kWave * kGatherBatch) {
+    int32_t w[kGatherBatch];
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u) {
+      int32_t k = k0 + lane + u * kWave;
+      w[u] = k < e1 ? R.col[k] : -1;
+    }
+    uint32_t x[kGatherBatch];
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u) {
+      x[u] = 0;
+      if ((uint32_t)w[u] < n) {
+        if (kSrc == 0) x[u] = sent_first(acc, w[u]);
+        else if (kSrc == 1) x[u] = sent_word(pv[w[u]], w[u], cur, vmask, pbit);
+        else x[u] = sent_word(R.pv[(uint32_t)w[u] - base], w[u], cur, vmask, pbit);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u) {
+      int32_t k = k0 + lane + u * kWave;
+      if (k < e1 && x[u] != 0) atomicMax(&best[R.roff[k]], x[u]);
+    }
+  }
+}
+
+// Resident mode: one pass over the wave's rows.
+// kFirst: the reset sweep over every edge (successors send their id if
+// accepting; every row is written).  kLocal: only edges to rows of this
+// block, from the block's LDS values (values move along in-block edges
+// without a round trip to memory).  Otherwise: only edges to rows of other
+// blocks, gathered from memory.  A row is written only when its value grows.
 template <bool kFirst, bool kLocal>
 __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, const WaveRows& W, int wib, int lane,
                                    uint32_t cur, uint32_t* acc_count) {
@@ -411,35 +449,14 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, const 
   uint32_t* best = R.best[wib];
   g_u32* pv = (g_u32*)a.pv;
   g_cu8* gacc = (g_cu8*)acc;
-  const uint32_t n = (uint32_t)a.n, vmask = a.val_mask, pbit = a.par_bit;
-  const uint32_t base = (uint32_t)W.rb0, span = (uint32_t)(W.rb1 - W.rb0);
+  const uint32_t vmask = a.val_mask;
+  const uint32_t base = (uint32_t)W.rb0;
 #pragma unroll
   for (int j = 0; j < kResRowsPerLane; ++j) best[lane + j * kWave] = 0;
   wave_lds_sync();
-  for (int32_t k0 = W.we0; k0 < W.we1; k0 += kWave * kGatherBatch) {
-    int32_t w[kGatherBatch];
-#pragma unroll
-    for (int u = 0; u < kGatherBatch; ++u) {
-      int32_t k = k0 + lane + u * kWave;
-      w[u] = k < W.we1 ? R.col[k] : -1;
-    }
-    uint32_t x[kGatherBatch];
-#pragma unroll
-    for (int u = 0; u < kGatherBatch; ++u) {
-      x[u] = 0;
-      if ((uint32_t)w[u] < n) {
-        const uint32_t local = (uint32_t)w[u] - base;
-        if (kFirst) x[u] = sent_first(acc, w[u]);
-        else if (local < span) x[u] = sent_word(R.pv[local], w[u], cur, vmask, pbit);
-        else if (!kLocal) x[u] = sent_word(pv[w[u]], w[u], cur, vmask, pbit);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kGatherBatch; ++u) {
-      int32_t k = k0 + lane + u * kWave;
-      if (k < W.we1 && x[u] != 0) atomicMax(&best[R.roff[k]], x[u]);
-    }
-  }
+  if (kFirst) gather_range<0>(acc, W.we0, W.we1, best, a, base, lane, cur);
+  else if (kLocal) gather_range<2>(acc, W.wr, W.we1, best, a, base, lane, cur);
+  else gather_range<1>(acc, W.we0, W.wr, best, a, base, lane, cur);
   wave_lds_sync();
   uint32_t changed = 0, nacc = 0;
 #pragma unroll
@@ -469,33 +486,59 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, const 
   return __ballot(changed) != 0;
 }
 
-// One sweep of the block's rows.  Every thread of the block calls it.  In
-// resident mode up to kLocalPasses LDS-only passes over in-block edges follow
-// the sweep (they stop early once a pass changes nothing in the block).
+// One sweep of the block's rows.  Every thread of the block calls it.
+// Resident mode: the pass over edges to other blocks' rows (every edge in the
+// reset sweep), then up to kLocalPasses LDS passes over in-block edges, which
+// stop once a pass changes nothing in the block.  *local_fix (block-uniform)
+// records that the last LDS pass changed nothing: while it holds and the first
+// pass changes nothing, the block's values are at the fixpoint of the values
+// gathered, and the LDS passes are skipped.
 template <bool kFirst>
 __device__ uint32_t sweep_rows(const LoopArgs& a, const uint8_t* acc, const WaveRows W, int wib, int lane,
-                               uint32_t cur, uint32_t* acc_count) {
+                               uint32_t cur, uint32_t* acc_count, bool* local_fix) {
   __shared__ uint32_t s_any;
   if (W.resident) {
     uint32_t ch = sweep_resident<kFirst, false>(a, acc, W, wib, lane, cur, acc_count);
-    for (int p = 0; p < kLocalPasses; ++p) {
-      if (threadIdx.x == 0) s_any = 0;
-      __syncthreads();  // the block's LDS values of the previous pass are complete
-      const uint32_t lc = sweep_resident<false, true>(a, acc, W, wib, lane, cur, nullptr);
-      if (lc && lane == 0) atomicOr(&s_any, 1u);
-      ch |= lc;
-      __syncthreads();
-      const uint32_t any = s_any;
-      __syncthreads();
-      if (!any) break;
+    if (threadIdx.x == 0) s_any = 0;
+    __syncthreads();
+    if (ch && lane == 0) atomicOr(&s_any, 1u);
+    __syncthreads();
+    const bool run = kFirst || s_any != 0 || !*local_fix;
+    *local_fix = false;
+    if (run) {
+      for (int p = 0; p < kLocalPasses; ++p) {
+        __syncthreads();  // every thread has read s_any; the previous pass's LDS values are complete
+        if (threadIdx.x == 0) s_any = 0;
+        __syncthreads();
+        const uint32_t lc = sweep_resident<false, true>(a, acc, W, wib, lane, cur, nullptr);
+        if (lc && lane == 0) atomicOr(&s_any, 1u);
+        ch |= lc;
+        __syncthreads();
+        if (s_any == 0) {
+          *local_fix = true;
+          break;
+        }
+      }
+    } else {
+      *local_fix = true;
     }
+    __syncthreads();  // every thread has read s_any
     return ch;
   }
   uint32_t ch = 0;
   if (W.r1 > W.r0) {
-    // Tiles in decreasing row order: values mostly flow from high ids to low.
-    for (int64_t t0 = W.r0 + ((W.r1 - W.r0 - 1) / kTileRows) * kTileRows; t0 >= W.r0; t0 -= kTileRows)
-      ch |= sweep_tile<kFirst>(a, acc, t0, min(W.r1, t0 + kTileRows), g_lds.tile[wib], lane, cur, acc_count);
+    // Tiles in the order values travel: a row takes values from its
+    // successors, so when most edges point to higher rows values flow from
+    // high ids to low and the tiles go downwards, otherwise upwards; a tile
+    // then sees the values its neighbours produced earlier in the same sweep.
+    const int64_t last = W.r0 + ((W.r1 - W.r0 - 1) / kTileRows) * kTileRows;
+    if (W.ascending) {
+      for (int64_t t0 = W.r0; t0 <= last; t0 += kTileRows)
+        ch |= sweep_tile<kFirst>(a, acc, t0, min(W.r1, t0 + kTileRows), g_lds.tile[wib], lane, cur, acc_count);
+    } else {
+      for (int64_t t0 = last; t0 >= W.r0; t0 -= kTileRows)
+        ch |= sweep_tile<kFirst>(a, acc, t0, min(W.r1, t0 + kTileRows), g_lds.tile[wib], lane, cur, acc_count);
+    }
   }
   return ch;
 }
@@ -600,22 +643,77 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     const int32_t eb0 = a.row_ptr[rb0], eb1 = a.row_ptr[rb1];
     W.resident = !a.force_stream && a.n <= (1 << 24) && rows_per_wave <= kResWaveRows &&
                  (int64_t)eb1 - eb0 <= kResEdges;
-    if (W.resident) {
-      // Stage the block's column slice and each edge's row offset in its wave.
-      for (int32_t k = threadIdx.x; k < eb1 - eb0; k += kBlock) S.res.col[k] = a.col[eb0 + k];
-      for (int64_t r = rb0 + threadIdx.x; r < rb1; r += kBlock) {
-        const uint8_t off = (uint8_t)((r - rb0) % rows_per_wave);
-        const int32_t k1 = a.row_ptr[r + 1] - eb0;
-        for (int32_t k = a.row_ptr[r] - eb0; k < k1; ++k) S.res.roff[k] = off;
+    W.wr = 0;
+    W.ascending = false;
+    if (!W.resident) {
+      // Direction of the block's edges, from up to 8 rows per thread.
+      __shared__ uint32_t s_dir[2];
+      if (threadIdx.x < 2) s_dir[threadIdx.x] = 0;
+      __syncthreads();
+      uint32_t down = 0, up = 0;
+      for (int64_t r = rb0 + threadIdx.x, i = 0; r < rb1 && i < 8; r += kBlock, ++i) {
+        const int32_t k1 = a.row_ptr[r + 1];
+        for (int32_t k = a.row_ptr[r]; k < k1; ++k) {
+          if ((int64_t)a.col[k] < r) ++down;
+          else if ((int64_t)a.col[k] > r) ++up;
+        }
       }
-      W.we0 = a.row_ptr[W.r0] - eb0;
-      W.we1 = a.row_ptr[W.r1] - eb0;
-    }
-    __syncthreads();
-    if (W.resident) {
-      sort_gather_batches(W.we0, W.we1, lane);
+      down = wave_sum_u32(down);
+      up = wave_sum_u32(up);
+      if (lane == 0) {
+        atomicAdd(&s_dir[0], down);
+        atomicAdd(&s_dir[1], up);
+      }
+      __syncthreads();
+      W.ascending = s_dir[0] > s_dir[1];
       __syncthreads();
     }
+    if (W.resident) {
+      // Each wave stages its rows' edges (column and row offset in the wave)
+      // in its part of the block's slice: edges to rows of other blocks first,
+      // then edges to rows of this block, so that a sweep can gather only the
+      // former and the LDS passes walk only the latter.
+      W.we0 = a.row_ptr[W.r0] - eb0;
+      W.we1 = a.row_ptr[W.r1] - eb0;
+      const uint32_t base = (uint32_t)rb0, span = (uint32_t)(rb1 - rb0);
+      const uint64_t below = lane ? (~0ull >> (kWave - lane)) : 0ull;
+      int32_t nrem = 0, nloc = 0;
+      for (int64_t rc = W.r0; rc < W.r1; rc += kWave) {
+        const int64_t r = rc + lane;
+        int32_t k = 0, k1 = 0;
+        if (r < W.r1) {
+          k = a.row_ptr[r];
+          k1 = a.row_ptr[r + 1];
+        }
+        const uint8_t off = (uint8_t)(r - W.r0);
+        for (;;) {
+          const bool act = k < k1;
+          if (__ballot(act) == 0) break;
+          const int32_t t = act ? a.col[k] : 0;
+          const bool rem = act && (uint32_t)t - base >= span;
+          const bool loc = act && !rem;
+          const uint64_t mr = __ballot(rem), ml = __ballot(loc);
+          if (rem) {
+            const int32_t q = W.we0 + nrem + __popcll(mr & below);
+            S.res.col[q] = t;
+            S.res.roff[q] = off;
+          }
+          if (loc) {
+            const int32_t q = W.we1 - 1 - nloc - __popcll(ml & below);
+            S.res.col[q] = t;
+            S.res.roff[q] = off;
+          }
+          nrem += __popcll(mr);
+          nloc += __popcll(ml);
+          k += act ? 1 : 0;
+        }
+      }
+      W.wr = W.we0 + nrem;
+      wave_lds_sync();
+      sort_gather_batches(W.we0, W.wr, lane);
+      sort_gather_batches(W.wr, W.we1, lane);
+    }
+    __syncthreads();
   }
 
   Grid<C> g;
@@ -696,6 +794,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     uint32_t nacc = 0;       // accepting rows of this block in A_k (reset sweep)
     uint32_t cnt_k = 0;      // |A_k|
     int64_t s = 0;           // sweeps of this block in iteration k
+    bool local_fix = false;  // resident: the block's values are at the fixpoint of its in-block edges
     // One loop for both fixpoint controls, so that each sweep variant is
     // inlined once.
     //  - sync: a grid barrier after every sweep carries the changed count.
@@ -747,7 +846,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
         d0 = s_red[1];
         __syncthreads();
       }
-      const uint32_t c1 = sweep_rows<true>(a, acc, W, wib, lane, cur, &nacc);
+      const uint32_t c1 = sweep_rows<true>(a, acc, W, wib, lane, cur, &nacc, &local_fix);
       s = 1;
       if (!report(block_any(c1), d0)) goto aborted;
     }
@@ -792,7 +891,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
         if (cmd == 2) goto aborted;
         if (cmd == 1) break;
       }
-      const uint32_t c2 = sweep_rows<false>(a, acc, W, wib, lane, cur, nullptr);
+      const uint32_t c2 = sweep_rows<false>(a, acc, W, wib, lane, cur, nullptr, &local_fix);
       s++;
       if (!report(block_any(c2), d0)) goto aborted;
     }
