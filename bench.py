@@ -336,6 +336,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--sync-sweeps", action="store_true", help="grid barrier after every sweep")
     ap.add_argument("--stream", action="store_true", help="stream the CSR every sweep (no on-chip staging)")
+    ap.add_argument("--push", action="store_true", help="frontier rounds over the transposed CSR")
     ap.add_argument("--batch-count", type=int, default=4096, help="graphs in the config-4 batch")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a plain copy of known size and exit")
     ap.add_argument("--copy-mib", type=int, default=1024)
@@ -380,7 +381,7 @@ def main():
     res = mc.new_result(dev)
     stream = torch.cuda.current_stream()
     flags = mc.MAP_FLAG_NO_TRACE_DIGEST | (mc.MAP_FLAG_SYNC_SWEEPS if args.sync_sweeps else 0) | \
-        (mc.MAP_FLAG_STREAM if args.stream else 0)
+        (mc.MAP_FLAG_STREAM if args.stream else 0) | (mc.MAP_FLAG_PUSH if args.push else 0)
 
     def step(ev=None):
         rc = mc.map_build_csr(n, src, dst, row_ptr, col, rrow_ptr, rcol, status, ws)

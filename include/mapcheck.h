@@ -60,10 +60,11 @@ extern "C" {
 #define MAP_PENDING 1          /* engine: the job has not finished yet */
 
 /* Flags (bitwise or; 0 = automatic choice). */
-#define MAP_FLAG_DENSE_ONLY 0x1u /* never switch to the sparse (frontier) sweep */
+#define MAP_FLAG_DENSE_ONLY 0x1u /* pull sweeps only: overrides MAP_FLAG_PUSH */
 #define MAP_FLAG_NO_TRACE_DIGEST 0x2u /* leave the digest column of the trace 0 */
 #define MAP_FLAG_STREAM 0x4u /* never stage the CSR in on-chip memory: stream it every sweep */
 #define MAP_FLAG_SYNC_SWEEPS 0x8u /* a grid-wide barrier after every sweep (no asynchronous sweeps) */
+#define MAP_FLAG_PUSH 0x10u /* frontier sweeps over the transposed CSR (needs rrow_ptr, rcol) */
 
 /* Result of map_propagate / map_detect, written to device memory (32 bytes). */
 typedef struct map_result {
@@ -92,7 +93,7 @@ size_t map_workspace_bytes(int32_t n, int64_t m, uint32_t flags);
  *   col        device int32[m] out: 0-based successor indices.
  *   rrow_ptr,  device int32[n+1] / int32[m] out, or both NULL: the transposed
  *   rcol       CSR (row v lists the predecessors of vertex v+1), used by the
- *              sparse sweep.
+ *              frontier sweeps (MAP_FLAG_PUSH).
  *   status     device int32 out: MAP_OK, or MAP_ERANGE_DEV if an id lies
  *              outside 1..n (the CSR contents are then unspecified).
  * Duplicate edges and self-loops are kept.  Column order within a row is
@@ -107,7 +108,11 @@ int map_build_csr(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, 
  * largest accepting value that reached it through a successor; repeat until no
  * value improves), for a given accepting set.
  *   row_ptr, col    device pull CSR from map_build_csr.
- *   rrow_ptr, rcol  device transposed CSR, or NULL (dense sweeps only).
+ *   rrow_ptr, rcol  device transposed CSR, or NULL.  With MAP_FLAG_PUSH the
+ *                   fixpoint runs in frontier rounds over it (each vertex
+ *                   whose value grew raises its predecessors with an atomic
+ *                   max; one grid barrier per round) instead of pull sweeps;
+ *                   MAP_EINVAL if the flag is given without it.
  *   accepting       device uint8[n], not modified.
  *   map_out         device int32[n] out: map(v) for id v at index v-1.
  *   result          device map_result out: sweeps and status (found, witness

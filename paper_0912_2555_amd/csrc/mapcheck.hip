@@ -48,7 +48,8 @@ constexpr int kLocalPasses = 4;                         // resident mode: LDS-on
 constexpr int kSortSlots = 1024;                        // resident mode: bitonic sort width (>= 64 * kGatherBatch)
 constexpr int kSortPerLane = kSortSlots / kWave;
 static_assert(kSortSlots >= kWave * kGatherBatch, "sort must cover a gather batch");
-constexpr uint32_t kAllFlags = MAP_FLAG_DENSE_ONLY | MAP_FLAG_NO_TRACE_DIGEST | MAP_FLAG_STREAM | MAP_FLAG_SYNC_SWEEPS;
+constexpr uint32_t kAllFlags =
+    MAP_FLAG_DENSE_ONLY | MAP_FLAG_NO_TRACE_DIGEST | MAP_FLAG_STREAM | MAP_FLAG_SYNC_SWEEPS | MAP_FLAG_PUSH;
 constexpr uint32_t kAccBit = 0x80000000u;
 
 // Global-memory views of device pointers, for out-of-line functions where the
@@ -99,6 +100,8 @@ struct CtrlT {
   uint32_t pad1[31];
   alignas(128) uint32_t done;
   uint32_t pad2[31];
+  alignas(128) uint32_t fcount[2];  // push: entries appended to frontier 0 / 1
+  uint32_t pad3[30];
   unsigned long long quiet[Q];
 };
 using Ctrl = CtrlT<kMaxBlocks>;
@@ -260,6 +263,11 @@ struct LoopArgs {
   int32_t sync_sweeps;   // 1: a grid barrier after every sweep instead of the asynchronous fixpoint
   uint32_t val_mask;     // bits of a packed word holding the map value
   uint32_t par_bit;      // bit holding the iteration parity (0: untagged, n >= 2^30)
+  int32_t push;          // 1: frontier sweeps over the transposed CSR (barrier per round)
+  const int32_t* rrow_ptr;  // push: transposed CSR (row w = predecessors of w)
+  const int32_t* rcol;
+  int32_t* front[2];     // push: frontier lists, int32[n] each
+  uint32_t* mark;        // push: round in which a vertex last joined a frontier
 };
 
 // Row ownership: the rows are cut into one contiguous range per block and,
@@ -612,6 +620,20 @@ __device__ void sort_gather_batches(int32_t we0, int32_t we1, int lane) {
   }
 }
 
+// Appends v (where take) to frontier F with one counter update per wave;
+// returns the number appended by the wave (wave-uniform).
+__device__ __forceinline__ uint32_t frontier_append(int32_t* F, uint32_t* cnt, bool take, int32_t v, int lane) {
+  const uint64_t m = __ballot(take);
+  if (m == 0) return 0;
+  const int first = __ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0;
+  if (lane == first) base = __hip_atomic_fetch_add(cnt, (uint32_t)__popcll(m), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  base = (uint32_t)__shfl((int)base, first, kWave);
+  const uint64_t below = lane ? (~0ull >> (kWave - lane)) : 0ull;
+  if (take) F[base + (uint32_t)__popcll(m & below)] = v;
+  return (uint32_t)__popcll(m);
+}
+
 // The whole MAP computation for one graph, run by `nb` cooperating blocks of
 // which this is block `b`; `logical` is the block's position in row order.
 // Every block of the set must call it; c is the set's zeroed control block.
@@ -755,6 +777,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
   };
 
   uint32_t count_prev = 0;  // |A_k| of the last completed iteration
+  uint32_t rtag = 0;        // push: frontier round, the same in every block
   int32_t k = 0;
   int64_t total_sweeps = 0;
   int32_t status = MAP_OK, found = 0, witness = 0;
@@ -773,6 +796,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     uint32_t cnt = 0;
     for (int64_t v = W.r0 + lane; v < W.r1; v += kWave) {
       a.pv[v] = 0u;
+      if (a.push) a.mark[v] = 0u;
       if (!a.propagate) {
         uint8_t x = a.acc_in[v] ? 1 : 0;
         a.accw[v] = x;
@@ -834,6 +858,91 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
       }
       return true;
     };
+    // Sum over the block of a per-wave count (every thread gets it).
+    auto block_sum_waves = [&](uint32_t x) {
+      if (lane == 0) s_red[wib] = x;
+      __syncthreads();
+      uint32_t t = 0;
+      for (int i = 0; i < kWavesPerBlock; ++i) t += s_red[i];
+      __syncthreads();
+      return t;
+    };
+    if (sync && a.push) {
+      // Frontier rounds over the transposed CSR: every vertex whose value grew
+      // sends its new value to each predecessor with an atomic max on the
+      // packed word (same accepting bit and parity, so the words compare by
+      // value); the predecessors that grew form the next frontier.  A grid
+      // barrier ends each round and carries the size of the next frontier.
+      // The reset gives every row map 0 and puts the accepting rows in the
+      // first frontier (they send their own id).
+      g_u32* pvg = (g_u32*)a.pv;
+      g_cu8* gacc = (g_cu8*)acc;
+      ++rtag;
+      if (b == 0 && threadIdx.x == 0) st_agent(&c->fcount[1], 0u);
+      uint32_t napp = 0;
+      for (int64_t v0 = W.r0; v0 < W.r1; v0 += kWave) {
+        const int64_t v = v0 + lane;
+        uint32_t isacc = 0;
+        if (v < W.r1) {
+          isacc = gacc[v] ? 1u : 0u;
+          pvg[v] = (isacc << 31) | cur;
+          if (isacc) a.mark[v] = rtag;
+        }
+        nacc += isacc;
+        napp += frontier_append(a.front[0], &c->fcount[0], isacc != 0, (int32_t)v, lane);
+      }
+      if (!a.propagate) block_add_count(nacc, g.gen % kSets);
+      uint32_t bapp = block_sum_waves(napp);
+      if (!grid_sync(g, bapp, &tot)) goto aborted;
+      if (!a.propagate) cnt_k = read_count((g.gen - 1) % kSets);
+      s = 1;
+      int fc = 0;
+      uint32_t S = tot;
+      const int64_t gw = (int64_t)b * kWavesPerBlock + wib, nw = (int64_t)nb * kWavesPerBlock;
+      while (S > 0) {
+        if (s > (int64_t)a.n + 1) { status = MAP_ENOTCONVERGED; break; }
+        ++rtag;
+        // This round reads frontier fc; its counter is next written in the
+        // round after (the barrier ending this round orders the clear).
+        if (b == 0 && threadIdx.x == 0) st_agent(&c->fcount[fc], 0u);
+        const int32_t* F = a.front[fc];
+        int32_t* Fn = a.front[fc ^ 1];
+        uint32_t* cn = &c->fcount[fc ^ 1];
+        napp = 0;
+        for (int64_t i0 = gw * kWave; i0 < (int64_t)S; i0 += nw * kWave) {
+          const int64_t i = i0 + lane;
+          int32_t k = 0, k1 = 0;
+          uint32_t x = 0;
+          if (i < (int64_t)S) {
+            const int32_t w = F[i];
+            x = sent_word(pvg[w], w, cur, a.val_mask, a.par_bit);
+            if (x) {
+              k = a.rrow_ptr[w];
+              k1 = a.rrow_ptr[w + 1];
+            }
+          }
+          for (;;) {
+            const bool act = k < k1;
+            if (__ballot(act) == 0) break;
+            bool grew = false;
+            int32_t v = 0;
+            if (act) {
+              v = a.rcol[k++];
+              const uint32_t word = ((gacc[v] ? 1u : 0u) << 31) | cur | x;
+              const uint32_t old = __hip_atomic_fetch_max(&a.pv[v], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              grew = (old & a.val_mask) < x &&
+                     __hip_atomic_exchange(&a.mark[v], rtag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != rtag;
+            }
+            napp += frontier_append(Fn, cn, grew, v, lane);
+          }
+        }
+        bapp = block_sum_waves(napp);
+        if (!grid_sync(g, bapp, &tot)) goto aborted;
+        S = tot;
+        fc ^= 1;
+        s++;
+      }
+    } else {
     {
       // The reset sweep of iteration k.
       uint32_t d0 = 0;
@@ -894,6 +1003,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
       const uint32_t c2 = sweep_rows<false>(a, acc, W, wib, lane, cur, nullptr, &local_fix);
       s++;
       if (!report(block_any(c2), d0)) goto aborted;
+    }
     }
     // Asynchronous mode: |A_k| is reduced together with the detect pass (same
     // barrier epoch).
@@ -1083,6 +1193,11 @@ __device__ LoopArgs gang_args(int32_t n, const int32_t* row_ptr, const int32_t* 
   a.sync_sweeps = (flags & MAP_FLAG_SYNC_SWEEPS) ? 1 : 0;
   a.val_mask = n < (1 << 30) ? 0x3fffffffu : kValMask;
   a.par_bit = n < (1 << 30) ? 0x40000000u : 0u;
+  a.push = 0;
+  a.rrow_ptr = nullptr;
+  a.rcol = nullptr;
+  a.front[0] = a.front[1] = nullptr;
+  a.mark = nullptr;
   return a;
 }
 
@@ -1674,7 +1789,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 bool sizes_ok(int32_t n, int64_t m) { return n >= 1 && n <= 0x7ffffffe && m >= 0 && m <= 0x7fffffff; }
 
 struct Layout {
-  size_t ctrl, pv, accw, cursor, sums, total;
+  size_t ctrl, pv, accw, front0, front1, mark, cursor, sums, total;
 };
 
 Layout layout(int32_t n) {
@@ -1688,6 +1803,13 @@ Layout layout(int32_t n) {
   off += align256((size_t)n * 4);
   L.accw = off;
   off += align256((size_t)n);
+  // frontier sweeps
+  L.front0 = off;
+  off += align256((size_t)n * 4);
+  L.front1 = off;
+  off += align256((size_t)n * 4);
+  L.mark = off;
+  off += align256((size_t)n * 4);
   size_t end_loop = off;
   // CSR build (shares the region after ctrl)
   off = region;
@@ -1912,11 +2034,28 @@ static int loop_common(int32_t n, const int32_t* row_ptr, const int32_t* col, co
   return MAP_OK;
 }
 
+// Frontier sweeps (MAP_FLAG_PUSH, not with MAP_FLAG_DENSE_ONLY) need the
+// transposed CSR; they run with a barrier per round and read the values from
+// memory (no LDS-resident rows).
+static int push_setup(LoopArgs& a, const int32_t* rrow_ptr, const int32_t* rcol, uint32_t flags, void* ws) {
+  if (!(flags & MAP_FLAG_PUSH) || (flags & MAP_FLAG_DENSE_ONLY)) return MAP_OK;
+  if (!rrow_ptr || !rcol) return MAP_EINVAL;
+  const Layout L = layout(a.n);
+  char* w = static_cast<char*>(ws);
+  a.push = 1;
+  a.rrow_ptr = rrow_ptr;
+  a.rcol = rcol;
+  a.front[0] = reinterpret_cast<int32_t*>(w + L.front0);
+  a.front[1] = reinterpret_cast<int32_t*>(w + L.front1);
+  a.mark = reinterpret_cast<uint32_t*>(w + L.mark);
+  a.force_stream = 1;
+  a.sync_sweeps = 1;
+  return MAP_OK;
+}
+
 int map_propagate(int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* rrow_ptr, const int32_t* rcol,
                   const uint8_t* accepting, int32_t* map_out, map_result* result, uint32_t flags, void* ws,
                   size_t ws_bytes, void* stream) {
-  (void)rrow_ptr;
-  (void)rcol;
   if (flags & ~kAllFlags) return MAP_EINVAL;
   if (!map_out) return MAP_EINVAL;
   LoopArgs a;
@@ -1926,6 +2065,8 @@ int map_propagate(int32_t n, const int32_t* row_ptr, const int32_t* col, const i
   a.force_stream = (flags & MAP_FLAG_STREAM) ? 1 : 0;
   a.sync_sweeps = (flags & MAP_FLAG_SYNC_SWEEPS) ? 1 : 0;
   a.map_out = map_out;
+  rc = push_setup(a, rrow_ptr, rcol, flags, ws);
+  if (rc) return rc;
   return launch_loop(a, reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -1933,8 +2074,6 @@ int map_detect(int32_t n, const int32_t* row_ptr, const int32_t* col, const int3
                const uint8_t* accepting0, map_result* result, uint64_t* trace, int32_t trace_cap,
                uint8_t* accepting_out, int32_t max_iterations, uint32_t flags, void* ws, size_t ws_bytes,
                void* stream) {
-  (void)rrow_ptr;
-  (void)rcol;
   if (flags & ~kAllFlags) return MAP_EINVAL;
   if (trace && trace_cap < 0) return MAP_EINVAL;
   LoopArgs a;
@@ -1948,6 +2087,8 @@ int map_detect(int32_t n, const int32_t* row_ptr, const int32_t* col, const int3
   a.digest = (trace && !(flags & MAP_FLAG_NO_TRACE_DIGEST)) ? 1 : 0;
   a.force_stream = (flags & MAP_FLAG_STREAM) ? 1 : 0;
   a.sync_sweeps = (flags & MAP_FLAG_SYNC_SWEEPS) ? 1 : 0;
+  rc = push_setup(a, rrow_ptr, rcol, flags, ws);
+  if (rc) return rc;
   return launch_loop(a, reinterpret_cast<hipStream_t>(stream));
 }
 

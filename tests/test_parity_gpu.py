@@ -135,26 +135,49 @@ def test_config2_reduced(mc, n, planted):
     _, ref = check_detect(mc, g, csr)
     if planted:
         assert ref.found == 1
+    check_detect(mc, g, csr, flags=mc.MAP_FLAG_PUSH, ref=ref)
 
 
 def test_config3_reduced(mc):
     g = synth.config3(n=1 << 18)
     csr = mc.build_csr(g.n, g.src, g.dst)
-    check_detect(mc, g, csr)
+    _, ref = check_detect(mc, g, csr)
     check_propagate_all(mc, g, csr, max_k=2)
+    check_detect(mc, g, csr, flags=mc.MAP_FLAG_PUSH, ref=ref)
 
 
 @pytest.mark.parametrize("g", [c for c in _random_cases() if c.n >= 64] + [synth.config1(), synth.config1(dag=True),
                                synth.config2(seed=4, n=1 << 15)], ids=lambda g: g.name)
-@pytest.mark.parametrize("mode", ["sync", "sync+stream"])
+@pytest.mark.parametrize("mode", ["sync", "sync+stream", "push"])
 def test_barrier_per_sweep(mc, g, mode):
-    """The same results with a grid barrier after every sweep (no asynchronous sweeps)."""
-    flags = mc.MAP_FLAG_SYNC_SWEEPS | (mc.MAP_FLAG_STREAM if "stream" in mode else 0)
+    """The same results with a grid barrier after every sweep (no asynchronous
+    sweeps), and with frontier rounds over the transposed CSR."""
+    if mode == "push":
+        flags = mc.MAP_FLAG_PUSH
+    else:
+        flags = mc.MAP_FLAG_SYNC_SWEEPS | (mc.MAP_FLAG_STREAM if "stream" in mode else 0)
     csr = mc.build_csr(g.n, g.src, g.dst)
     check_detect(mc, g, csr, flags=flags)
     ref = oracle.map_detect(g, mode="desc", maps_cap=1)
     got, res = mc.propagate(csr, g.acc, flags=flags)
     assert res.status == 0 and np.array_equal(got.cpu().numpy(), ref.maps[0])
+
+
+def test_push_edge_cases_and_flags(mc):
+    """Frontier rounds on degenerate graphs; the flag needs the transposed CSR;
+    MAP_FLAG_DENSE_ONLY overrides it."""
+    cases = [synth.from_edges(1, [], [1], "n1-acc"), synth.from_edges(1, [(1, 1)], [1], "n1-loop"),
+             synth.from_edges(300, [], [5, 17, 299], "no-edges"),
+             synth.from_edges(5, [(1, 2), (2, 3), (3, 1), (3, 4), (4, 5)], [2, 4, 5], "hand"),
+             synth.from_edges(6, [(1, 2), (2, 1), (1, 2), (3, 3), (4, 5), (5, 6), (6, 4)], [1, 2, 3, 6], "dups")]
+    for g in cases:
+        check_detect(mc, g, flags=mc.MAP_FLAG_PUSH)
+        check_detect(mc, g, flags=mc.MAP_FLAG_PUSH | mc.MAP_FLAG_DENSE_ONLY)
+    g = synth.config1()
+    csr = mc.build_csr(g.n, g.src, g.dst, transposed=False)
+    with pytest.raises(mc.MapError) as e:
+        mc.detect(csr, g.acc, flags=mc.MAP_FLAG_PUSH)
+    assert e.value.status == mc.MAP_EINVAL
 
 
 # ------------------------------------------------------------- edge cases
