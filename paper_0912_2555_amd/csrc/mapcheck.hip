@@ -287,8 +287,12 @@ struct TileLds {
 };
 
 struct ResLds {
-  int32_t col[kResEdges];
-  uint8_t roff[kResEdges];
+  // Staged edges of each wave: first those to rows of other blocks, as
+  // (successor << 8) | row offset in the wave, sorted by successor in gather
+  // batches; then those to rows of this block, as successor - block base,
+  // grouped by row in row order.
+  uint32_t e[kResEdges];
+  uint16_t lrow[kWavesPerBlock * kResWaveRows];  // first in-block edge of each row of the block
   uint32_t best[kWavesPerBlock][kResWaveRows];
   uint32_t pv[kWavesPerBlock * kResWaveRows];  // the block's own packed values (row - block base)
 };
@@ -408,83 +412,123 @@ __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int64_t r0
   return __ballot(changed) != 0;
 }
 
-// Resident mode: one pass over a range of the wave's staged edges, folding
-// what each edge's successor sends into best[row] with LDS atomic max.
-// kSrc 0: first sweep of an iteration (successors send their id if
-// accepting); 1: successors owned by other blocks, gathered from memory;
-// 2: successors owned by this block, read from the block's LDS values.
+// Resident mode: one pass over the wave's staged edges to rows of other
+// blocks, folding what each successor sends into best[row] with LDS atomic
+// max.  kSrc 0: first sweep of an iteration (successors send their id if
+// accepting); 1: the successors' packed values, gathered from memory.
 template <int kSrc>
 __device__ __forceinline__ void gather_range(const uint8_t* acc, int32_t e0, int32_t e1, uint32_t* best,
-                                             const LoopArgs& a, uint32_t base, int lane, uint32_t cur) {
+                                             const LoopArgs& a, int lane, uint32_t cur) {
   ResLds& R = g_lds.res;
   g_u32* pv = (g_u32*)a.pv;
   const uint32_t n = (uint32_t)a.n, vmask = a.val_mask, pbit = a.par_bit;
   for (int32_t k0 = e0; k0 < e1; k0 += kWave * kGatherBatch) {
-    int32_t w[kGatherBatch];
+    uint32_t e[kGatherBatch];
 #pragma unroll
     for (int u = 0; u < kGatherBatch; ++u) {
-      int32_t k = k0 + lane + u * kWave;
-      w[u] = k < e1 ? R.col[k] : -1;
+      const int32_t k = k0 + lane + u * kWave;
+      e[u] = k < e1 ? R.e[k] : 0xffffffffu;
     }
     uint32_t x[kGatherBatch];
 #pragma unroll
     for (int u = 0; u < kGatherBatch; ++u) {
       x[u] = 0;
-      if ((uint32_t)w[u] < n) {
-        if (kSrc == 0) x[u] = sent_first(acc, w[u]);
-        else if (kSrc == 1) x[u] = sent_word(pv[w[u]], w[u], cur, vmask, pbit);
-        else x[u] = sent_word(R.pv[(uint32_t)w[u] - base], w[u], cur, vmask, pbit);
+      const uint32_t w = e[u] >> 8;
+      if (e[u] != 0xffffffffu && w < n) {
+        if (kSrc == 0) x[u] = sent_first(acc, (int32_t)w);
+        else x[u] = sent_word(pv[w], (int32_t)w, cur, vmask, pbit);
       }
     }
 #pragma unroll
     for (int u = 0; u < kGatherBatch; ++u) {
-      int32_t k = k0 + lane + u * kWave;
-      if (k < e1 && x[u] != 0) atomicMax(&best[R.roff[k]], x[u]);
+      if (x[u] != 0) atomicMax(&best[e[u] & 0xffu], x[u]);
     }
   }
 }
 
-// Resident mode: one pass over the wave's rows.
-// kFirst: the reset sweep over every edge (successors send their id if
-// accepting; every row is written).  kLocal: only edges to rows of this
-// block, from the block's LDS values (values move along in-block edges
-// without a round trip to memory).  Otherwise: only edges to rows of other
-// blocks, gathered from memory.  A row is written only when its value grows.
-template <bool kFirst, bool kLocal>
+// Rows of the wave in the order values travel: a row takes values from its
+// successors, so when the block's edges mostly point to higher rows values
+// flow downwards and the rows go from high to low.
+__device__ __forceinline__ int row_step(const WaveRows& W, int jj) {
+  return W.ascending ? jj : kResRowsPerLane - 1 - jj;
+}
+
+// Resident mode, edges to rows of this block: every lane folds the successors
+// of its own rows from the block's LDS values, row by row in the order values
+// travel, so rows raised earlier in the pass are seen later in it.  No
+// atomics: a row's in-block edges are contiguous.  Returns nonzero
+// (wave-uniform) if some row grew.
+__device__ uint32_t local_pass(const LoopArgs& a, const WaveRows& W, int lane, uint32_t cur) {
+  ResLds& R = g_lds.res;
+  g_u32* pv = (g_u32*)a.pv;
+  const uint32_t vmask = a.val_mask, pbit = a.par_bit, base = (uint32_t)W.rb0;
+  const int32_t nrow = (int32_t)(W.r1 - W.r0), r0 = (int32_t)(W.r0 - W.rb0);
+  uint32_t changed = 0;
+#pragma unroll
+  for (int jj = 0; jj < kResRowsPerLane; ++jj) {
+    const int32_t i = lane + row_step(W, jj) * kWave;
+    if (i < nrow) {
+      const int32_t li = r0 + i;
+      const int32_t k1 = i + 1 < nrow ? (int32_t)R.lrow[li + 1] : W.we1;
+      uint32_t b = 0;
+      for (int32_t k = R.lrow[li]; k < k1; ++k) {
+        const uint32_t t = R.e[k];
+        b = max(b, sent_word(R.pv[t], (int32_t)(base + t), cur, vmask, pbit));
+      }
+      const uint32_t old = R.pv[li];
+      if (b > (old & vmask)) {
+        const uint32_t x = (old & ~vmask) | b;
+        pv[(int64_t)base + li] = x;
+        R.pv[li] = x;
+        changed = 1;
+      }
+    }
+  }
+  return __ballot(changed) != 0;
+}
+
+// Resident mode: the pass over the wave's edges to other blocks' rows.
+// kFirst: the reset sweep, which also folds the in-block edges (successors
+// send their id if accepting) and writes every row.  Otherwise a row is
+// written only when its value grows.  Returns nonzero (wave-uniform) if some
+// row changed.
+template <bool kFirst>
 __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, const WaveRows& W, int wib, int lane,
                                    uint32_t cur, uint32_t* acc_count) {
   ResLds& R = g_lds.res;
   uint32_t* best = R.best[wib];
   g_u32* pv = (g_u32*)a.pv;
   g_cu8* gacc = (g_cu8*)acc;
-  const uint32_t vmask = a.val_mask;
-  const uint32_t base = (uint32_t)W.rb0;
+  const uint32_t vmask = a.val_mask, base = (uint32_t)W.rb0;
+  const int32_t nrow = (int32_t)(W.r1 - W.r0), r0 = (int32_t)(W.r0 - W.rb0);
 #pragma unroll
   for (int j = 0; j < kResRowsPerLane; ++j) best[lane + j * kWave] = 0;
   wave_lds_sync();
-  if (kFirst) gather_range<0>(acc, W.we0, W.we1, best, a, base, lane, cur);
-  else if (kLocal) gather_range<2>(acc, W.wr, W.we1, best, a, base, lane, cur);
-  else gather_range<1>(acc, W.we0, W.wr, best, a, base, lane, cur);
+  gather_range<kFirst ? 0 : 1>(acc, W.we0, W.wr, best, a, lane, cur);
   wave_lds_sync();
   uint32_t changed = 0, nacc = 0;
 #pragma unroll
   for (int j = 0; j < kResRowsPerLane; ++j) {
-    int64_t v = W.r0 + lane + j * kWave;
-    if (v < W.r1) {
-      uint32_t b = best[lane + j * kWave];
+    const int32_t i = lane + j * kWave;
+    if (i < nrow) {
+      const int32_t li = r0 + i;
+      const int64_t v = (int64_t)base + li;
+      uint32_t b = best[i];
       if (kFirst) {
+        const int32_t k1 = i + 1 < nrow ? (int32_t)R.lrow[li + 1] : W.we1;
+        for (int32_t k = R.lrow[li]; k < k1; ++k) b = max(b, sent_first(acc, (int32_t)(base + R.e[k])));
         uint32_t isacc = gacc[v] ? 1u : 0u;
         nacc += isacc;
         const uint32_t x = (isacc << 31) | cur | b;
         pv[v] = x;
-        R.pv[v - W.rb0] = x;
+        R.pv[li] = x;
         changed |= (b | isacc) != 0;
       } else {
-        const uint32_t old = R.pv[v - W.rb0];
+        const uint32_t old = R.pv[li];
         if (b > (old & vmask)) {
           const uint32_t x = (old & ~vmask) | b;
           pv[v] = x;
-          R.pv[v - W.rb0] = x;
+          R.pv[li] = x;
           changed = 1;
         }
       }
@@ -506,7 +550,7 @@ __device__ uint32_t sweep_rows(const LoopArgs& a, const uint8_t* acc, const Wave
                                uint32_t cur, uint32_t* acc_count, bool* local_fix) {
   __shared__ uint32_t s_any;
   if (W.resident) {
-    uint32_t ch = sweep_resident<kFirst, false>(a, acc, W, wib, lane, cur, acc_count);
+    uint32_t ch = sweep_resident<kFirst>(a, acc, W, wib, lane, cur, acc_count);
     if (threadIdx.x == 0) s_any = 0;
     __syncthreads();
     if (ch && lane == 0) atomicOr(&s_any, 1u);
@@ -518,7 +562,7 @@ __device__ uint32_t sweep_rows(const LoopArgs& a, const uint8_t* acc, const Wave
         __syncthreads();  // every thread has read s_any; the previous pass's LDS values are complete
         if (threadIdx.x == 0) s_any = 0;
         __syncthreads();
-        const uint32_t lc = sweep_resident<false, true>(a, acc, W, wib, lane, cur, nullptr);
+        const uint32_t lc = local_pass(a, W, lane, cur);
         if (lc && lane == 0) atomicOr(&s_any, 1u);
         ch |= lc;
         __syncthreads();
@@ -578,7 +622,7 @@ __device__ void sort_gather_batches(int32_t we0, int32_t we1, int lane) {
 #pragma unroll
     for (int u = 0; u < kSortPerLane; ++u) {
       const int i = lane + u * kWave;
-      key[u] = i < cnt ? ((uint32_t)R.col[k0 + i] << 8) | R.roff[k0 + i] : 0xffffffffu;
+      key[u] = i < cnt ? R.e[k0 + i] : 0xffffffffu;
     }
 #pragma unroll
     for (int k = 2; k <= kSortSlots; k <<= 1) {
@@ -612,10 +656,7 @@ __device__ void sort_gather_batches(int32_t we0, int32_t we1, int lane) {
 #pragma unroll
     for (int u = 0; u < kSortPerLane; ++u) {
       const int i = lane + u * kWave;
-      if (i < cnt) {
-        R.col[k0 + i] = (int32_t)(key[u] >> 8);
-        R.roff[k0 + i] = (uint8_t)(key[u] & 0xffu);
-      }
+      if (i < cnt) R.e[k0 + i] = key[u];
     }
   }
 }
@@ -666,8 +707,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     W.resident = !a.force_stream && a.n <= (1 << 24) && rows_per_wave <= kResWaveRows &&
                  (int64_t)eb1 - eb0 <= kResEdges;
     W.wr = 0;
-    W.ascending = false;
-    if (!W.resident) {
+    {
       // Direction of the block's edges, from up to 8 rows per thread.
       __shared__ uint32_t s_dir[2];
       if (threadIdx.x < 2) s_dir[threadIdx.x] = 0;
@@ -691,15 +731,21 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
       __syncthreads();
     }
     if (W.resident) {
-      // Each wave stages its rows' edges (column and row offset in the wave)
-      // in its part of the block's slice: edges to rows of other blocks first,
-      // then edges to rows of this block, so that a sweep can gather only the
-      // former and the LDS passes walk only the latter.
+      // Each wave stages its rows' edges in its part of the block's slice:
+      // first the edges to rows of other blocks (gathered from memory each
+      // sweep), then the edges to rows of this block grouped by row (folded
+      // from LDS by the row's lane).
       W.we0 = a.row_ptr[W.r0] - eb0;
       W.we1 = a.row_ptr[W.r1] - eb0;
       const uint32_t base = (uint32_t)rb0, span = (uint32_t)(rb1 - rb0);
       const uint64_t below = lane ? (~0ull >> (kWave - lane)) : 0ull;
-      int32_t nrem = 0, nloc = 0;
+      uint32_t nr = 0;
+      for (int64_t r = W.r0 + lane; r < W.r1; r += kWave) {
+        const int32_t k1 = a.row_ptr[r + 1];
+        for (int32_t k = a.row_ptr[r]; k < k1; ++k) nr += (uint32_t)a.col[k] - base >= span ? 1u : 0u;
+      }
+      W.wr = W.we0 + (int32_t)wave_sum_u32(nr);
+      int32_t nrem = 0, lrun = W.wr;
       for (int64_t rc = W.r0; rc < W.r1; rc += kWave) {
         const int64_t r = rc + lane;
         int32_t k = 0, k1 = 0;
@@ -707,33 +753,31 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
           k = a.row_ptr[r];
           k1 = a.row_ptr[r + 1];
         }
-        const uint8_t off = (uint8_t)(r - W.r0);
+        uint32_t dl = 0;
+        for (int32_t kk = k; kk < k1; ++kk) dl += (uint32_t)a.col[kk] - base < span ? 1u : 0u;
+        uint32_t incl = dl;
+        for (int off = 1; off < kWave; off <<= 1) {
+          const uint32_t y = (uint32_t)__shfl_up((int)incl, off, kWave);
+          if (lane >= off) incl += y;
+        }
+        int32_t lpos = lrun + (int32_t)(incl - dl);
+        if (r < W.r1) S.res.lrow[r - rb0] = (uint16_t)lpos;
+        lrun += (int32_t)__shfl((int)incl, kWave - 1, kWave);
+        const uint32_t off = (uint32_t)(r - W.r0);
         for (;;) {
           const bool act = k < k1;
           if (__ballot(act) == 0) break;
           const int32_t t = act ? a.col[k] : 0;
           const bool rem = act && (uint32_t)t - base >= span;
-          const bool loc = act && !rem;
-          const uint64_t mr = __ballot(rem), ml = __ballot(loc);
-          if (rem) {
-            const int32_t q = W.we0 + nrem + __popcll(mr & below);
-            S.res.col[q] = t;
-            S.res.roff[q] = off;
-          }
-          if (loc) {
-            const int32_t q = W.we1 - 1 - nloc - __popcll(ml & below);
-            S.res.col[q] = t;
-            S.res.roff[q] = off;
-          }
+          const uint64_t mr = __ballot(rem);
+          if (rem) S.res.e[W.we0 + nrem + __popcll(mr & below)] = ((uint32_t)t << 8) | off;
           nrem += __popcll(mr);
-          nloc += __popcll(ml);
+          if (act && !rem) S.res.e[lpos++] = (uint32_t)t - base;
           k += act ? 1 : 0;
         }
       }
-      W.wr = W.we0 + nrem;
       wave_lds_sync();
       sort_gather_batches(W.we0, W.wr, lane);
-      sort_gather_batches(W.wr, W.we1, lane);
     }
     __syncthreads();
   }
