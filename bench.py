@@ -415,6 +415,7 @@ def main():
     gteps = k * m / (ms_step * 1e-3) / 1e9
     alg_bytes = r.sweeps * sweep_bytes(n, m) + k * 4 * n
     achieved = alg_bytes / (detect_ms * 1e-3) / 1e9
+    traffic = counted_traffic(args.workload, flags)
     gold = golden_for(args.workload)
     exact = None
     if gold is not None:
@@ -433,7 +434,8 @@ def main():
         "gteps_scan": round(r.sweeps * m / (detect_ms * 1e-3) / 1e9, 4),
         "roofline": {"bound": "hbm", "kernel": "map_loop_kernel", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": counted_traffic(args.workload, flags),
+                     "traffic": traffic,
+                     "traffic_gbs": round(traffic / (detect_ms * 1e-3) / 1e9, 2) if traffic else None,
                      "bytes_per_launch": int(alg_bytes)},
     }
     if not args.no_cpu_baseline:
