@@ -86,7 +86,7 @@ struct alignas(128) Line64 {
 // graph, or the gang of blocks that solves one graph of a batch.  Q bounds the
 // number of blocks in the set.
 template <int Q>
-struct CtrlT {
+struct alignas(256) CtrlT {
   Line64 grp[kMaxGroups];  // barrier arrivals per group: high 32 = arrivals, low 32 = payload sum
   Line64 top;              // arrivals of the group leaders
   alignas(128) uint32_t gen;       // barrier generation
@@ -108,7 +108,10 @@ using Ctrl = CtrlT<kMaxBlocks>;
 using GangCtrl = CtrlT<kMaxGang>;
 constexpr size_t kCtrlBytes = 32768;
 static_assert(sizeof(Ctrl) <= kCtrlBytes, "ctrl block too large");
-constexpr size_t kGangCtrlBytes = (sizeof(GangCtrl) + 255) & ~(size_t)255;
+constexpr size_t kGangCtrlBytes = sizeof(GangCtrl);
+// Arrays of control blocks are indexed with GangCtrl pointers and cleared in
+// kGangCtrlBytes units: the two strides must agree.
+static_assert(kGangCtrlBytes % 256 == 0, "control blocks are 256-byte multiples");
 
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -877,6 +880,10 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     //    fixpoint: block 0 then publishes done = k.
     const uint32_t tag = (uint32_t)k;
     uint32_t d_seen = 0xffffffffu;  // async: counter value of this block's last quiet sweep (wave 0)
+    // |A_k| <= |A_{k-1}| (detect); any accepting set has at most n vertices (propagate).
+    const int64_t acnt = a.propagate ? (int64_t)a.n : (int64_t)count_prev;
+    const int64_t sweep_cap =
+        acnt + 1 > (INT64_MAX / 4) / (int64_t)a.n ? INT64_MAX : 2 * (int64_t)a.n * (acnt + 1) + 16;
     // After a sweep: the barrier (sync) or the change / quiet report (async).
     // Returns false when the launch must stop.
     auto report = [&](uint32_t any, uint32_t d0) -> bool {
@@ -896,7 +903,11 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
         }
       }
       if (wib == 0) d_seen = any ? 0xffffffffu : d0;
-      if (s > 4 * (int64_t)a.n + 16) {  // unreachable for a monotone fixpoint: safety net
+      // Safety net, unreachable for a monotone fixpoint: every change raises a
+      // row to one of at most |A_k| + 1 values, so the blocks make at most
+      // n (|A_k| + 1) changing sweeps together, and a block sweeps after its
+      // own changes and after the counter moves, at most twice that plus one.
+      if (s > sweep_cap) {
         if (threadIdx.x == 0) st_agent((uint32_t*)&c->abort, 1u);
         return false;
       }
