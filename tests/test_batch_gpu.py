@@ -60,13 +60,15 @@ def test_batch_largest_first_and_repeat(mc, graphs):
     assert [x.verdict for x in a] == [x.verdict for x in b]
 
 
-@pytest.mark.parametrize("policy", ["gang4", "mixed"])
+@pytest.mark.parametrize("policy", ["gang4", "mixed", "wide"])
 def test_batch_gangs(mc, graphs, policy):
     gs, refs = graphs
     if policy == "gang4":
         gang = [4] * len(gs)
-    else:
+    elif policy == "mixed":
         gang = [1 if g.n < 20000 else min(16, 1 + g.n // 20000) for g in gs]
+    else:  # gangs beyond 64 workgroups, up to more than the grid holds (clamped by the library)
+        gang = [[96, 200, 1000][i % 3] for i in range(len(gs))]
     _check(mc, gs, refs, gang=gang)
 
 
