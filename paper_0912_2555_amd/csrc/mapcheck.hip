@@ -707,7 +707,9 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
   W.we0 = W.we1 = 0;
   {
     const int32_t eb0 = a.row_ptr[rb0], eb1 = a.row_ptr[rb1];
-    W.resident = !a.force_stream && a.n <= (1 << 24) && rows_per_wave <= kResWaveRows &&
+    // n < 2^24 keeps every staged remote key (successor << 8 | row offset)
+    // below 0xffffffff, the padding key of the sort and the gather.
+    W.resident = !a.force_stream && a.n < (1 << 24) && rows_per_wave <= kResWaveRows &&
                  (int64_t)eb1 - eb0 <= kResEdges;
     W.wr = 0;
     {
