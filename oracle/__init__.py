@@ -20,6 +20,8 @@ digest(map)             order-independent 64-bit digest of a map vector
 jacobi_steps(g, acc)    the vector after every jacobi pass
 tarjan(g)               accepting-cycle verdict from strongly connected components
 ndfs(g)                 accepting-cycle verdict from nested depth-first search
+lasso(g, w, init)       counterexample: shortest path init -> w, then shortest
+                        cycle through w (breadth-first search over successors)
 """
 from __future__ import annotations
 
@@ -71,6 +73,9 @@ def _load():
         lib.oracle_ndfs.restype = ctypes.c_int
         lib.oracle_jacobi_steps.argtypes = [i32, i64, _i32p, _i32p, _u8p, vp, i64]
         lib.oracle_jacobi_steps.restype = i64
+        lib.oracle_lasso.argtypes = [i32, i64, _i32p, _i32p, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                     vp, i32]
+        lib.oracle_lasso.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -166,3 +171,26 @@ def ndfs(g, acc=None) -> int:
     if rc < 0:
         raise ValueError(f"oracle_ndfs failed rc={rc}")
     return rc
+
+
+@dataclass
+class Lasso:
+    status: str              # "ok", "no_path" (init does not reach w, or w on no cycle), "no_space"
+    stem_len: int            # edges init -> w (0 without init); -1 if not found
+    cycle_len: int           # edges of a shortest cycle through w; -1 if none
+    path: np.ndarray | None  # int32 ids: init, ..., w, ..., w (stem_len + cycle_len + 1), or None
+
+
+def lasso(g, w: int, init: int = 0, cap: int | None = None) -> Lasso:
+    """Counterexample for witness ``w``: shortest stem from ``init`` (0: none), shortest cycle through w."""
+    src, dst, _ = _arrays(g, np.zeros(g.n, np.uint8))
+    cap = g.n + g.n + 1 if cap is None else cap
+    path = np.zeros(max(cap, 1), np.int32)
+    s_len, c_len = ctypes.c_int32(0), ctypes.c_int32(0)
+    rc = _load().oracle_lasso(g.n, len(src), src, dst, int(w), int(init), ctypes.byref(s_len), ctypes.byref(c_len),
+                              path.ctypes.data, cap)
+    if rc not in (0, -8, -9):
+        raise ValueError(f"oracle_lasso failed rc={rc}")
+    status = {0: "ok", -8: "no_path", -9: "no_space"}[rc]
+    s, c = int(s_len.value), int(c_len.value)
+    return Lasso(status, s, c, path[:s + c + 1].copy() if rc == 0 else None)

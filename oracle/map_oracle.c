@@ -446,3 +446,89 @@ int oracle_ndfs(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, co
     adj_free(&s);
     return rc;
 }
+
+/* -------------------------------------------------- counterexample --- */
+/*
+ * A counterexample for a reported cycle (the paper lists counterexample
+ * generation as missing from the tool, Section 5): a lasso made of a shortest
+ * path from an initial vertex `init` to the witness w and a shortest cycle
+ * through w, both along edges of G, found by breadth-first search over
+ * successors.  Their lengths are unique; the vertices are one valid choice
+ * (the first discovery in edge-list order).
+ *
+ * path receives init = s_0, ..., s_S = w, c_1, ..., c_L = w (S + L + 1 ids);
+ * without an initial vertex (init == 0) or with init == w, S = 0.
+ * Returns OR_OK; OR_ENOPATH when init does not reach w or w lies on no cycle
+ * (a length not found is -1); OR_ENOSPC when cap is below S + L + 1 (both
+ * lengths set, path untouched); OR_EINVAL on bad input, OR_ENOMEM.
+ */
+#define OR_ENOPATH -8
+#define OR_ENOSPC -9
+
+/* Breadth-first search from `from` until an edge enters `to`; parent[v] is
+ * the vertex v was first reached from (0: not reached).  `from` itself is
+ * not marked, so from == to finds a shortest cycle.  Returns the number of
+ * edges of a shortest path of >= 1 edge, or -1; *last is the vertex whose
+ * edge entered `to`. */
+static int32_t bfs_to(const adj_t *s, int32_t from, int32_t to, int32_t *parent, int32_t *queue,
+                      int32_t *last) {
+    memset(parent, 0, ((size_t)s->n + 1) * sizeof(int32_t));
+    int64_t head = 0, tail = 0;
+    queue[tail++] = from;
+    int32_t dist_head = 0;
+    /* level boundaries: queue[level_end] starts the next level */
+    int64_t level_end = tail;
+    while (head < tail) {
+        int32_t u = queue[head++];
+        for (int64_t j = s->off[u]; j < s->off[u + 1]; ++j) {
+            int32_t v = s->nb[j];
+            if (v == to) { *last = u; return dist_head + 1; }
+            if (v != from && parent[v] == 0) {
+                parent[v] = u;
+                queue[tail++] = v;
+            }
+        }
+        if (head == level_end) { dist_head++; level_end = tail; }
+    }
+    return -1;
+}
+
+int oracle_lasso(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t w, int32_t init,
+                 int32_t *stem_len, int32_t *cycle_len, int32_t *path, int32_t cap) {
+    int rc = check_ids(n, m, src, dst);
+    if (rc) return rc;
+    if (w < 1 || w > n || init < 0 || init > n || cap < 0 || !stem_len || !cycle_len) return OR_EINVAL;
+    adj_t s;
+    rc = adj_build(n, m, src, dst, 1, &s);
+    if (rc) return rc;
+    int32_t *parent = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    int32_t *queue = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    int32_t *stem = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    if (!parent || !queue || !stem) { rc = OR_ENOMEM; goto out; }
+    int32_t S = 0, L, last = 0;
+    *stem_len = *cycle_len = -1;
+    if (init != 0 && init != w) {
+        S = bfs_to(&s, init, w, parent, queue, &last);
+        if (S < 0) { rc = OR_ENOPATH; goto out; }
+        /* s_S = w, s_{S-1} = last, s_{i-1} = parent[s_i]; parent[init] stays 0 */
+        stem[S] = w;
+        for (int32_t i = S - 1, x = last; i >= 0; --i) { stem[i] = x; x = parent[x]; }
+    } else {
+        stem[0] = w;
+    }
+    *stem_len = S;
+    L = bfs_to(&s, w, w, parent, queue, &last);
+    if (L < 0) { rc = OR_ENOPATH; goto out; }
+    *cycle_len = L;
+    if ((int64_t)S + L + 1 > cap) { rc = OR_ENOSPC; goto out; }
+    for (int32_t i = 0; i <= S; ++i) path[i] = stem[i];
+    path[S + L] = w;
+    for (int32_t i = S + L - 1, x = last; i > S; --i) { path[i] = x; x = parent[x]; }
+    rc = OR_OK;
+out:
+    free(parent);
+    free(queue);
+    free(stem);
+    adj_free(&s);
+    return rc;
+}
