@@ -45,6 +45,9 @@ WORKLOADS = {
            "config5", None),
     "c4": ("config 4: 4,096 independent config-1 DAG graphs, N log-uniform in [1e3,1e6], odd ones with a "
            "planted accepting 64-cycle, one persistent launch vs the plain per-graph loop", "config4", None),
+    "lasso": ("counterexample on config 2 variant A: shortest path from vertex 1 to the witness found by "
+              "map_detect, then shortest cycle through it (breadth-first search, one cooperative launch)",
+              "config2", True),
 }
 
 
@@ -289,6 +292,89 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_lasso(args):
+    """Counterexample search on config 2A: map_detect gives the witness (untimed), then map_lasso is timed."""
+    import torch
+    import paper_0912_2555_amd as mc
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    g = make_graph("lasso")
+    n, m = g.n, g.m
+    print(f"[bench] lasso on c2A n={n} m={m}", file=sys.stderr, flush=True)
+    csr = mc.build_csr(n, g.src, g.dst, transposed=False, device=dev)
+    out = mc.detect(csr, g.acc)
+    w = out.result.witness
+    gold = golden_for("c2A")
+    if out.result.found != 1 or (gold is not None and w != gold["witness"]):
+        raise RuntimeError(f"map_detect gave found={out.result.found} witness={w}")
+    init = 1
+    ws = mc.workspace(n, m, device=dev)
+    cap = 2 * n + 1
+    path = torch.zeros(cap, dtype=torch.int32, device=dev)
+    res = torch.zeros(8, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        rc = mc.map_lasso(n, csr.row_ptr, csr.col, w, init, path, res, ws)
+        if rc:
+            raise mc.MapError(rc, "map_lasso")
+        if ev is not None:
+            ev[1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(events[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    a = res.cpu().numpy()
+    status, stem, cyc, plen = (int(x) for x in a[:4])
+    scanned, levels = int(a[4:6].view(np.int64)[0]), int(a[6])
+    if status != mc.MAP_OK:
+        raise RuntimeError(f"map_lasso status {status}")
+    import oracle
+    t = time.perf_counter()
+    ref = oracle.lasso(g, w, init)
+    cpu_s = time.perf_counter() - t
+    p = path[:plen].cpu().numpy().astype(np.int64)
+    key = np.sort(g.src.astype(np.int64) * (n + 1) + g.dst)
+    pk = p[:-1] * (n + 1) + p[1:]
+    idx = np.minimum(np.searchsorted(key, pk), len(key) - 1)
+    valid = bool(np.array_equal(key[idx], pk) and p[0] == init and p[stem] == w and p[-1] == w)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    lasso_ms = float(np.mean([x.elapsed_time(y) for x, y in events]))
+    # two searches: each clears the n parent words; every examined edge reads its column and the
+    # target's parent word
+    alg_bytes = 2 * 4 * n + 8 * scanned
+    achieved = alg_bytes / (lasso_ms * 1e-3) / 1e9
+    result = {
+        "metric": METRIC, "value": round(1e3 / ms_step, 2), "unit": "lassos/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": WORKLOADS["lasso"][0], "key": "lasso", "n": n, "m": m, "witness": w, "init": init,
+                   "parallelism": "single GPU"},
+        "result": {"stem_len": stem, "cycle_len": cyc, "path_len": plen, "edges_scanned": scanned,
+                   "levels": levels, "path_valid": valid,
+                   "lengths_match_oracle": bool((stem, cyc) == (ref.stem_len, ref.cycle_len))},
+        "lasso_ms": round(lasso_ms, 4),
+        "roofline": {"bound": "hbm", "kernel": "map_lasso_kernel", "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": None, "bytes_per_launch": int(alg_bytes)},
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = {"value": round(1.0 / cpu_s, 2), "unit": "lassos/s", "cores": 1, "kind": "oracle",
+                                  "sample": f"one full lasso on c2A (stem from 1, cycle through {w}), "
+                                            f"{cpu_s * 1e3:.1f} ms wall on the host"}
+    print(json.dumps(result), flush=True)
+
+
 def counted_traffic(workload: str, flags: int):
     """HBM bytes per launch from the committed counter summary, or None.
 
@@ -359,6 +445,9 @@ def main():
         return
     if args.workload == "c5":
         bench_serve(args)
+        return
+    if args.workload == "lasso":
+        bench_lasso(args)
         return
 
     import torch

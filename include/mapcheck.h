@@ -57,6 +57,7 @@ extern "C" {
 #define MAP_ENOTCONVERGED (-5) /* device: iteration or sweep cap reached */
 #define MAP_ERANGE_DEV (-6)    /* device: an edge endpoint outside 1..n */
 #define MAP_EBUSY (-7)         /* engine: no free job slot or ticket space */
+#define MAP_ENOPATH (-8)       /* lasso: no path from the initial vertex, or no cycle through the witness */
 #define MAP_PENDING 1          /* engine: the job has not finished yet */
 
 /* Flags (bitwise or; 0 = automatic choice). */
@@ -145,6 +146,44 @@ int map_detect(int32_t n, const int32_t *row_ptr, const int32_t *col, const int3
                const int32_t *rcol, const uint8_t *accepting0, map_result *result, uint64_t *trace,
                int32_t trace_cap, uint8_t *accepting_out, int32_t max_iterations, uint32_t flags, void *ws,
                size_t ws_bytes, void *stream);
+
+/* Result of map_lasso (device memory, 32 bytes). */
+typedef struct map_lasso_result {
+  int32_t status;        /* MAP_OK, MAP_ENOPATH, MAP_ENOSPC (path_cap too small), MAP_ERANGE_DEV, MAP_EDEVICE */
+  int32_t stem_len;      /* edges of the path from init to the witness (0 without init); -1 if none */
+  int32_t cycle_len;     /* edges of the cycle through the witness; -1 if none or not searched */
+  int32_t path_len;      /* ids written to path: stem_len + cycle_len + 1 on MAP_OK, else 0 */
+  int64_t edges_scanned; /* edges examined by both searches */
+  int32_t levels;        /* breadth-first rounds of both searches */
+  int32_t reserved;
+} map_lasso_result;
+
+/*
+ * Counterexample for a reported cycle, which the paper lists as missing from
+ * its tool (Section 5): a lasso made of a shortest path in G from an initial
+ * vertex to the witness and a shortest cycle in G through the witness.  Both
+ * are found by breadth-first search over the successor rows of the pull CSR
+ * that map_detect uses, in one cooperative launch (a grid barrier per round).
+ * The two lengths are unique; the vertices are one valid choice, which may
+ * differ from run to run when several shortest paths exist.
+ *   row_ptr, col  device pull CSR of G from map_build_csr (row v = successors).
+ *   witness       1..n, typically map_result.witness of a found cycle.
+ *   init          1..n: the stem starts there; 0 (or == witness): no stem.
+ *   path          device int32[path_cap] out, ids: init = s_0, ..., s_S = witness,
+ *                 c_1, ..., c_L = witness.  Contents unspecified unless
+ *                 result->status == MAP_OK.  May be NULL when path_cap == 0.
+ *   result        device map_lasso_result out.  MAP_ENOPATH: init does not
+ *                 reach the witness (both lengths -1) or the witness lies on no
+ *                 cycle (cycle_len -1); MAP_ENOSPC: path_cap < stem_len +
+ *                 cycle_len + 1 (both lengths set, nothing written).
+ *   ws            workspace of at least map_workspace_bytes(n, m, 0) bytes; its
+ *                 contents from another call are not needed.
+ * Host errors: MAP_ERANGE (n), MAP_EINVAL (null pointer, witness or init out
+ * of range, path_cap < 0), MAP_ENOSPC (workspace).
+ */
+int map_lasso(int32_t n, const int32_t *row_ptr, const int32_t *col, int32_t witness, int32_t init,
+              int32_t *path, int32_t path_cap, map_lasso_result *result, void *ws, size_t ws_bytes,
+              void *stream);
 
 /* One graph of a batch (device memory; see map_detect_batch). */
 typedef struct map_graph_desc {

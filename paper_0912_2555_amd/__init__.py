@@ -11,8 +11,9 @@ The raw calls mirror the C names and never synchronize:
 ``map_build_csr(n, src, dst, row_ptr, col, rrow_ptr, rcol, status, ws)``
 ``map_propagate(n, row_ptr, col, rrow_ptr, rcol, accepting, map_out, result, flags, ws)``
 ``map_detect(n, row_ptr, col, rrow_ptr, rcol, accepting0, result, trace, accepting_out, max_iterations, flags, ws)``
+``map_lasso(n, row_ptr, col, witness, init, path, result, ws)``
 
-Convenience wrappers (``Csr``, ``build_csr``, ``propagate``, ``detect``)
+Convenience wrappers (``Csr``, ``build_csr``, ``propagate``, ``detect``, ``lasso``)
 allocate the tensors, call the raw entry points and synchronize when results
 are read back.
 
@@ -39,6 +40,7 @@ MAP_EDEVICE = -4
 MAP_ENOTCONVERGED = -5
 MAP_ERANGE_DEV = -6
 MAP_EBUSY = -7
+MAP_ENOPATH = -8
 MAP_PENDING = 1
 MAP_FLAG_DENSE_ONLY = 0x1
 MAP_FLAG_NO_TRACE_DIGEST = 0x2
@@ -48,7 +50,8 @@ MAP_FLAG_PUSH = 0x10
 
 EXPORTS = ("map_workspace_bytes", "map_build_csr", "map_propagate", "map_detect", "map_batch_workspace_bytes",
            "map_detect_batch", "map_job_scratch_bytes", "map_engine_create", "map_engine_workgroups",
-           "map_engine_submit", "map_engine_poll", "map_engine_stop", "map_engine_destroy", "map_strerror")
+           "map_engine_submit", "map_engine_poll", "map_engine_stop", "map_engine_destroy", "map_lasso",
+           "map_strerror")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_0912_2555_amd.build` "
@@ -64,6 +67,8 @@ _lib.map_propagate.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u32, _v
 _lib.map_propagate.restype = ctypes.c_int
 _lib.map_detect.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _i32, _u32, _vp, _sz, _vp]
 _lib.map_detect.restype = ctypes.c_int
+_lib.map_lasso.argtypes = [_i32, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _sz, _vp]
+_lib.map_lasso.restype = ctypes.c_int
 _lib.map_batch_workspace_bytes.argtypes = [_i32, _i64, _u32]
 _lib.map_batch_workspace_bytes.restype = _sz
 _lib.map_detect_batch.argtypes = [_i32, _vp, _vp, _vp, _i64, _u32, _vp, _sz, _vp]
@@ -154,6 +159,12 @@ def map_detect(n, row_ptr, col, rrow_ptr, rcol, accepting0, result, trace, accep
     return _lib.map_detect(n, _ptr(row_ptr), _ptr(col), _ptr(rrow_ptr), _ptr(rcol), _ptr(accepting0),
                            _ptr(result), _ptr(trace), cap, _ptr(accepting_out), max_iterations, flags, _ptr(ws),
                            0 if ws is None else ws.numel() * ws.element_size(), _stream(stream))
+
+
+def map_lasso(n, row_ptr, col, witness, init, path, result, ws, stream=None) -> int:
+    cap = 0 if path is None else int(path.numel())
+    return _lib.map_lasso(n, _ptr(row_ptr), _ptr(col), witness, init, _ptr(path), cap, _ptr(result), _ptr(ws),
+                          0 if ws is None else ws.numel() * ws.element_size(), _stream(stream))
 
 
 def map_batch_workspace_bytes(count: int, total_n: int, flags: int = 0) -> int:
@@ -265,6 +276,31 @@ def detect(csr: Csr, accepting0, trace_cap: int = 0, want_acc: bool = False, max
     if trace is not None:
         tr = trace.cpu().numpy().view(np.uint64)[:min(r.iterations, trace_cap)].copy()
     return DetectOut(r, tr, acc_out.cpu().numpy() if acc_out is not None else None)
+
+
+@dataclass
+class LassoOut:
+    status: int              # MAP_OK, MAP_ENOPATH, MAP_ENOSPC, MAP_ERANGE_DEV, MAP_EDEVICE
+    stem_len: int            # edges init -> witness (0 without init), -1 if none
+    cycle_len: int           # edges of the cycle through the witness, -1 if none
+    path: np.ndarray | None  # ids: init, ..., witness, ..., witness (MAP_OK only)
+    edges_scanned: int
+    levels: int
+
+
+def lasso(csr: Csr, witness: int, init: int = 0, cap: int | None = None, ws=None, stream=None) -> LassoOut:
+    """Counterexample for ``witness``: shortest path from ``init`` (0: none), shortest cycle through it."""
+    dev = csr.row_ptr.device
+    cap = 2 * csr.n + 1 if cap is None else cap
+    path = torch.zeros(max(cap, 1), dtype=torch.int32, device=dev)
+    res = torch.zeros(8, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = workspace(csr.n, csr.m, device=dev)
+    _check(map_lasso(csr.n, csr.row_ptr, csr.col, witness, init, path[:cap], res, ws, stream), "map_lasso")
+    a = res.cpu().numpy()
+    status, s, c, plen = (int(x) for x in a[:4])
+    scanned = int(a[4:6].view(np.int64)[0])
+    return LassoOut(status, s, c, path[:plen].cpu().numpy() if status == MAP_OK else None, scanned, int(a[6]))
 
 
 # ------------------------------------------------------------------ batches

@@ -100,8 +100,11 @@ struct alignas(256) CtrlT {
   uint32_t pad1[31];
   alignas(128) uint32_t done;
   uint32_t pad2[31];
-  alignas(128) uint32_t fcount[2];  // push: entries appended to frontier 0 / 1
-  uint32_t pad3[30];
+  alignas(128) uint32_t fcount[2];  // push and lasso: entries appended to frontier 0 / 1
+  uint32_t hit;                     // lasso: 1 + the vertex whose edge reached the target
+  uint32_t bad;                     // lasso: an edge endpoint outside 0..n-1 was read
+  unsigned long long scanned;       // lasso: edges examined
+  uint32_t pad3[26];
   unsigned long long quiet[Q];
 };
 using Ctrl = CtrlT<kMaxBlocks>;
@@ -1225,6 +1228,213 @@ __device__ __noinline__ void map_body_gang_sync(const LoopArgs& a, GangCtrl* c, 
   map_body<GangCtrl, false>(a, c, nb, rank, rank);
 }
 
+// --------------------------------------------------------- counterexample --
+
+// Arguments of the lasso search: a shortest path from `init` to the witness
+// and a shortest cycle through it, by breadth-first search over successors.
+struct LassoArgs {
+  int32_t n;
+  const int32_t* row_ptr;  // pull CSR of G: row v = successors of v
+  const int32_t* col;
+  int32_t w;               // witness, 0-based
+  int32_t init;            // initial vertex, 0-based, or -1
+  int32_t* path;           // ids out
+  int32_t cap;
+  map_lasso_result* result;
+  int32_t* parent;         // [n]: 0 unreached, 1 + the vertex it was reached from, -1 the start
+  int32_t* front[2];       // frontiers [n]
+  Ctrl* ctrl;
+};
+
+// Sum over the block of a per-wave u32 (every thread gets it).
+__device__ uint32_t lasso_block_sum(uint32_t x) {
+  __shared__ uint32_t s_part[kWavesPerBlock];
+  const int lane = threadIdx.x & (kWave - 1), wib = threadIdx.x / kWave;
+  if (lane == 0) s_part[wib] = x;
+  __syncthreads();
+  uint32_t t = 0;
+  for (int i = 0; i < kWavesPerBlock; ++i) t += s_part[i];
+  __syncthreads();
+  return t;
+}
+
+// Breadth-first search from `from` until an edge enters `to`, run by every
+// thread of the grid.  The start is marked reached (parent -1) but an edge
+// into `to` is taken before that mark is looked at, so from == to finds a
+// shortest cycle.  Each round expands one frontier: a wave takes 64 frontier
+// vertices, a lane walks its vertex's successors, an unreached successor is
+// claimed with a compare-and-swap on its parent word and appended to the next
+// frontier; an edge into `to` records its source in c->hit.  A grid barrier
+// ends each round and carries the size of the next frontier.  Returns the
+// length of a shortest path of >= 1 edge, 0 if `to` is not reached, -1 if a
+// barrier wait gave up (the launch must stop); *last (every block) is the
+// vertex whose edge entered `to`.
+__device__ int32_t lasso_bfs(const LassoArgs& a, Grid<Ctrl>& g, int32_t from, int32_t to, int32_t* last,
+                             unsigned long long* scanned, int32_t* levels) {
+  Ctrl* c = a.ctrl;
+  const int lane = threadIdx.x & (kWave - 1), wib = threadIdx.x / kWave;
+  const int64_t gw = (int64_t)g.rank * kWavesPerBlock + wib, nw = (int64_t)g.nblocks * kWavesPerBlock;
+  for (int64_t v = (int64_t)g.rank * kBlock + threadIdx.x; v < a.n; v += (int64_t)g.nblocks * kBlock)
+    a.parent[v] = 0;
+  if (g.rank == 0 && threadIdx.x == 0) {
+    st_agent(&c->hit, 0u);
+    st_agent(&c->fcount[0], 0u);
+    st_agent(&c->fcount[1], 0u);
+  }
+  if (!grid_sync(g, 0, nullptr)) return -1;
+  if (g.rank == 0 && threadIdx.x == 0) {
+    a.front[0][0] = from;
+    a.parent[from] = -1;
+  }
+  if (!grid_sync(g, 0, nullptr)) return -1;
+  uint32_t* parent = reinterpret_cast<uint32_t*>(a.parent);
+  uint32_t size = 1;
+  int fc = 0;
+  for (int32_t level = 1;; ++level) {
+    // This round reads frontier fc and appends to fc ^ 1, whose counter was
+    // cleared before the barrier that opened the round; fc's counter is
+    // appended to in the next round, after the barrier that closes this one.
+    if (g.rank == 0 && threadIdx.x == 0) st_agent(&c->fcount[fc], 0u);
+    const int32_t* F = a.front[fc];
+    int32_t* Fn = a.front[fc ^ 1];
+    uint32_t* cn = &c->fcount[fc ^ 1];
+    uint32_t napp = 0;
+    for (int64_t i0 = gw * kWave; i0 < (int64_t)size; i0 += nw * kWave) {
+      const int64_t i = i0 + lane;
+      int32_t u = 0, k = 0, k1 = 0;
+      if (i < (int64_t)size) {
+        u = F[i];
+        if ((uint32_t)u < (uint32_t)a.n) {
+          k = a.row_ptr[u];
+          k1 = a.row_ptr[u + 1];
+        } else {
+          st_agent(&c->bad, 1u);
+        }
+      }
+      for (;;) {
+        const bool act = k < k1;
+        if (__ballot(act) == 0) break;
+        bool take = false;
+        int32_t v = 0;
+        if (act) {
+          v = a.col[k++];
+          ++*scanned;
+          if ((uint32_t)v >= (uint32_t)a.n) {
+            st_agent(&c->bad, 1u);
+          } else if (v == to) {
+            uint32_t zero = 0;
+            __hip_atomic_compare_exchange_strong(&c->hit, &zero, (uint32_t)u + 1u, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } else if (ld_agent(&parent[v]) == 0u) {
+            uint32_t zero = 0;
+            take = __hip_atomic_compare_exchange_strong(&parent[v], &zero, (uint32_t)u + 1u, __ATOMIC_RELAXED,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+        napp += frontier_append(Fn, cn, take, v, lane);
+      }
+    }
+    uint32_t tot = 0;
+    if (!grid_sync(g, lasso_block_sum(napp), &tot)) return -1;
+    *levels += 1;
+    if (ld_agent(&c->bad)) return 0;
+    const uint32_t h = ld_agent(&c->hit);
+    if (h) {
+      *last = (int32_t)h - 1;
+      return level;
+    }
+    if (tot == 0) return 0;
+    size = tot;
+    fc ^= 1;
+  }
+}
+
+// Walks parent words back from `x` and writes path[hi], path[hi-1], ...,
+// path[lo] (ids); the word of the vertex written at path[lo] must name `root`.
+// Single thread.  Returns false if the chain does not end there.
+__device__ bool lasso_walk(const LassoArgs& a, int32_t x, int32_t hi, int32_t lo, int32_t root) {
+  for (int32_t i = hi; i >= lo; --i) {
+    if ((uint32_t)x >= (uint32_t)a.n) return false;
+    a.path[i] = x + 1;
+    const int32_t p = (int32_t)ld_agent((const uint32_t*)&a.parent[x]);
+    if (i == lo) return p == root + 1 || (p == -1 && x == root);
+    if (p <= 0) return false;
+    x = p - 1;
+  }
+  return true;
+}
+
+__global__ void __launch_bounds__(kBlock) map_lasso_kernel(LassoArgs a) {
+  Grid<Ctrl> g;
+  g.c = a.ctrl;
+  g.gen = 0;
+  g.nblocks = gridDim.x;
+  g.ngroups = min((int)gridDim.x, kMaxGroups);
+  g.group = blockIdx.x % g.ngroups;
+  g.group_size = gridDim.x / g.ngroups + ((blockIdx.x % g.ngroups) < (gridDim.x % g.ngroups) ? 1 : 0);
+  g.rank = blockIdx.x;
+  const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+  unsigned long long scanned = 0;
+  int32_t levels = 0, S = 0, L = -1, last = 0;
+  int32_t status = MAP_OK;
+  bool written = false;
+  if (a.init >= 0 && a.init != a.w) {
+    S = lasso_bfs(a, g, a.init, a.w, &last, &scanned, &levels);
+    if (S < 0) goto aborted;
+    if (S == 0) {
+      S = -1;
+      status = MAP_ENOPATH;
+    } else if (leader && (int64_t)S + 1 <= a.cap) {
+      // s_S = w, s_{S-1} = last, ..., s_0 = init (parent word -1)
+      a.path[S] = a.w + 1;
+      if (!lasso_walk(a, last, S - 1, 0, a.init)) status = MAP_EDEVICE;
+    }
+    // The stem's parent words are read above before the next search clears them.
+    if (!grid_sync(g, 0, nullptr)) goto aborted;
+  }
+  if (status == MAP_OK) {
+    L = lasso_bfs(a, g, a.w, a.w, &last, &scanned, &levels);
+    if (L < 0) goto aborted;
+    if (L == 0) {
+      L = -1;
+      status = MAP_ENOPATH;
+    } else if ((int64_t)S + L + 1 > a.cap) {
+      status = MAP_ENOSPC;
+    } else if (leader) {
+      // c_L = w, c_{L-1} = last, ..., c_1 (parent word names w)
+      a.path[S + L] = a.w + 1;
+      if (S == 0) a.path[0] = a.w + 1;
+      if (L > 1 && !lasso_walk(a, last, S + L - 1, S + 1, a.w)) status = MAP_EDEVICE;
+      if (L == 1 && last != a.w) status = MAP_EDEVICE;
+      written = status == MAP_OK;
+    }
+  }
+  {
+    // Edges examined: one atomic per wave, read after a last barrier.
+    const unsigned long long ws = wave_sum_u64(scanned);
+    if ((threadIdx.x & (kWave - 1)) == 0 && ws)
+      __hip_atomic_fetch_add(&a.ctrl->scanned, ws, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!grid_sync(g, 0, nullptr)) goto aborted;
+  }
+  if (leader) {
+    if (ld_agent(&a.ctrl->bad)) status = MAP_ERANGE_DEV;
+    map_lasso_result* r = a.result;
+    r->status = status;
+    r->stem_len = status == MAP_ENOPATH && S < 0 ? -1 : S;
+    r->cycle_len = L;
+    r->path_len = written && status == MAP_OK ? S + L + 1 : 0;
+    r->edges_scanned = (int64_t)__hip_atomic_load(&a.ctrl->scanned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    r->levels = levels;
+    r->reserved = 0;
+  }
+  return;
+aborted:
+  if (leader) {
+    a.result->status = MAP_EDEVICE;
+    a.result->path_len = 0;
+  }
+}
+
 // Loop arguments of one graph solved by a gang: scratch holds the packed
 // values (4n bytes, 256-aligned) followed by the working accepting flags.
 __device__ LoopArgs gang_args(int32_t n, const int32_t* row_ptr, const int32_t* col, const uint8_t* acc0,
@@ -2149,6 +2359,71 @@ int map_detect(int32_t n, const int32_t* row_ptr, const int32_t* col, const int3
   return launch_loop(a, reinterpret_cast<hipStream_t>(stream));
 }
 
+int map_lasso(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t witness, int32_t init, int32_t* path,
+              int32_t path_cap, map_lasso_result* result, void* ws, size_t ws_bytes, void* stream) {
+  if (n < 1 || n > 0x7ffffffe) return MAP_ERANGE;
+  if (!row_ptr || !col || !result || !ws || path_cap < 0 || (path_cap > 0 && !path)) return MAP_EINVAL;
+  if (witness < 1 || witness > n || init < 0 || init > n) return MAP_EINVAL;
+  const Layout L = layout(n);
+  if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return MAP_ENOSPC;
+  static std::mutex mu;
+  static int cache_cus[64], cache_per[64], cache_coop[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return MAP_EDEVICE;
+  int cus, per, coop;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (cache_cus[dev] == 0) {
+      int c = 0, nb = 0, co = 0;
+      if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return MAP_EDEVICE;
+      if (hipDeviceGetAttribute(&co, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) return MAP_EDEVICE;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(map_lasso_kernel), kBlock,
+                                                       0) != hipSuccess)
+        return MAP_EDEVICE;
+      if (c <= 0 || nb <= 0) return MAP_EDEVICE;
+      cache_cus[dev] = c;
+      cache_per[dev] = nb;
+      cache_coop[dev] = co;
+    }
+    cus = cache_cus[dev];
+    per = cache_per[dev];
+    coop = cache_coop[dev];
+  }
+  if (!coop) return MAP_EDEVICE;
+  // About one workgroup per 4096 vertices, at most one per CU: a round's
+  // frontier is usually far smaller than the graph, and fewer workgroups make
+  // the per-round barrier cheaper.
+  int64_t grid = ((int64_t)n + 4095) / 4096;
+  if (grid > (int64_t)cus * per) grid = (int64_t)cus * per;
+  if (grid > cus) grid = cus;
+  if (grid > kMaxBlocks) grid = kMaxBlocks;
+  if (grid >= kMaxGroups) grid -= grid % kMaxGroups;
+  if (grid < 1) grid = 1;
+  char* w = static_cast<char*>(ws);
+  LassoArgs a;
+  a.n = n;
+  a.row_ptr = row_ptr;
+  a.col = col;
+  a.w = witness - 1;
+  a.init = init - 1;
+  a.path = path;
+  a.cap = path_cap;
+  a.result = result;
+  a.parent = reinterpret_cast<int32_t*>(w + L.pv);
+  a.front[0] = reinterpret_cast<int32_t*>(w + L.front0);
+  a.front[1] = reinterpret_cast<int32_t*>(w + L.front1);
+  a.ctrl = reinterpret_cast<Ctrl*>(w + L.ctrl);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(fill_u32, dim3(8), dim3(256), 0, st, reinterpret_cast<uint32_t*>(a.ctrl),
+                     (int64_t)(kCtrlBytes / 4), 0u);
+  if (hipGetLastError() != hipSuccess) return MAP_EDEVICE;
+  void* args[] = {&a};
+  if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(map_lasso_kernel), dim3((unsigned)grid), dim3(kBlock),
+                                 args, 0, st) != hipSuccess)
+    return MAP_EDEVICE;
+  return MAP_OK;
+}
+
 size_t map_batch_workspace_bytes(int32_t count, int64_t total_n, uint32_t flags) {
   (void)flags;
   if (count < 1 || count > (1 << 24) || total_n < count || total_n > ((int64_t)1 << 40)) return 0;
@@ -2432,6 +2707,7 @@ const char* map_strerror(int status) {
     case MAP_ENOTCONVERGED: return "iteration or sweep cap reached";
     case MAP_ERANGE_DEV: return "edge endpoint outside 1..n";
     case MAP_EBUSY: return "engine has no free job slot or ticket space; poll finished jobs first";
+    case MAP_ENOPATH: return "no path from the initial vertex to the witness, or no cycle through the witness";
     case MAP_PENDING: return "job not finished yet";
     default: return "unknown status";
   }

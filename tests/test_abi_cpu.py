@@ -39,8 +39,8 @@ def test_exports_every_declared_symbol(lib):
     names = declared_functions()
     assert names == ["map_batch_workspace_bytes", "map_build_csr", "map_detect", "map_detect_batch",
                      "map_engine_create", "map_engine_destroy", "map_engine_poll", "map_engine_stop",
-                     "map_engine_submit", "map_engine_workgroups", "map_job_scratch_bytes", "map_propagate",
-                     "map_strerror", "map_workspace_bytes"]
+                     "map_engine_submit", "map_engine_workgroups", "map_job_scratch_bytes", "map_lasso",
+                     "map_propagate", "map_strerror", "map_workspace_bytes"]
     for name in names:
         assert hasattr(lib, name), name
 
@@ -51,8 +51,9 @@ def test_header_compiles_as_c():
     with tempfile.TemporaryDirectory() as d:
         src = os.path.join(d, "t.c")
         with open(src, "w") as f:
-            f.write('#include "mapcheck.h"\nint main(void){ map_result r; map_job j; (void)r; (void)j; '
-                    'return (int)sizeof(map_result) - 32 + (int)sizeof(map_job) - 72; }\n')
+            f.write('#include "mapcheck.h"\nint main(void){ map_result r; map_job j; map_lasso_result l; '
+                    '(void)r; (void)j; (void)l; return (int)sizeof(map_result) - 32 + (int)sizeof(map_job) - 72 '
+                    '+ (int)sizeof(map_lasso_result) - 32; }\n')
         subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
                                "-o", os.path.join(d, "t"), src])
         assert subprocess.call([os.path.join(d, "t")]) == 0
@@ -90,6 +91,25 @@ def test_host_side_errors_without_device(lib):
     assert lib.map_detect(5, fake, fake, None, None, fake, None, None, 0, None, 0, 0, fake, big, None) == MAP_EINVAL
     assert lib.map_detect(5, fake, fake, None, None, fake, fake, fake, -1, None, 0, 0, fake, big, None) == MAP_EINVAL
     assert lib.map_detect(5, fake, fake, None, None, fake, fake, None, 0, None, 0, 0, fake, 8, None) == MAP_ENOSPC
+
+
+def test_lasso_host_side_errors_without_device(lib):
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    lib.map_lasso.argtypes = [i32, vp, vp, i32, i32, vp, i32, vp, vp, sz, vp]
+    fake = ctypes.c_void_p(0x1000)
+    big = lib.map_workspace_bytes(5, 3, 0)
+    assert lib.map_lasso(0, fake, fake, 1, 0, fake, 8, fake, fake, big, None) == MAP_ERANGE
+    assert lib.map_lasso(5, None, fake, 1, 0, fake, 8, fake, fake, big, None) == MAP_EINVAL
+    assert lib.map_lasso(5, fake, fake, 1, 0, fake, 8, None, fake, big, None) == MAP_EINVAL
+    assert lib.map_lasso(5, fake, fake, 0, 0, fake, 8, fake, fake, big, None) == MAP_EINVAL   # witness 0
+    assert lib.map_lasso(5, fake, fake, 6, 0, fake, 8, fake, fake, big, None) == MAP_EINVAL   # witness > n
+    assert lib.map_lasso(5, fake, fake, 2, 6, fake, 8, fake, fake, big, None) == MAP_EINVAL   # init > n
+    assert lib.map_lasso(5, fake, fake, 2, -1, fake, 8, fake, fake, big, None) == MAP_EINVAL
+    assert lib.map_lasso(5, fake, fake, 2, 0, None, 8, fake, fake, big, None) == MAP_EINVAL   # path NULL, cap > 0
+    assert lib.map_lasso(5, fake, fake, 2, 0, fake, -1, fake, fake, big, None) == MAP_EINVAL
+    assert lib.map_lasso(5, fake, fake, 2, 0, fake, 8, fake, fake, 16, None) == MAP_ENOSPC
+    assert lib.map_lasso(5, fake, fake, 2, 0, fake, 8, fake, ctypes.c_void_p(0x1004), big, None) == MAP_ENOSPC
+    assert lib.map_strerror(-8).decode().startswith("no path")
 
 
 def test_strerror(lib):

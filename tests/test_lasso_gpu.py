@@ -1,0 +1,186 @@
+"""Parity of the counterexample search (map_lasso, through the C ABI) with the
+oracle's breadth-first lasso.
+
+The stem and cycle lengths are unique and compared exactly, with the status.
+The vertices are one of possibly several shortest paths: where the shortest
+path is unique (hand example, relabelled cycles) they are compared exactly,
+everywhere else every consecutive pair is checked to be an edge of G, the stem
+to start at the initial vertex and both parts to end at the witness.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import read_golden
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def mc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    import paper_0912_2555_amd as mc
+    return mc
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+STATUS = {"ok": 0, "no_path": -8, "no_space": -9}
+
+
+def check(mc, g, csr, w, init, cap=None, exact_path=False):
+    say("lasso", g.name or "graph", "n", g.n, "m", len(g.src), "w", w, "init", init, "cap", cap)
+    got = mc.lasso(csr, w, init, cap=cap)
+    want = oracle.lasso(g, w, init, cap=cap)
+    want_status = {"ok": mc.MAP_OK, "no_path": mc.MAP_ENOPATH, "no_space": mc.MAP_ENOSPC}[want.status]
+    assert got.status == want_status, (got, want)
+    assert (got.stem_len, got.cycle_len) == (want.stem_len, want.cycle_len), (got, want)
+    if got.status == mc.MAP_OK:
+        p = got.path.tolist()
+        assert len(p) == got.stem_len + got.cycle_len + 1
+        assert p[0] == (init if init not in (0, w) else w)
+        assert p[got.stem_len] == w and p[-1] == w
+        edges = set(zip(g.src.tolist(), g.dst.tolist())) if len(g.src) < 2_000_000 else None
+        if edges is not None:
+            for a, b in zip(p, p[1:]):
+                assert (a, b) in edges, (a, b)
+        else:
+            _check_edges_sorted(g, p)
+        if exact_path:
+            assert p == want.path.tolist()
+    return got
+
+
+def _check_edges_sorted(g, p):
+    key = g.src.astype(np.int64) * (g.n + 1) + g.dst
+    key = np.sort(key)
+    q = np.array(p, np.int64)
+    pk = q[:-1] * (g.n + 1) + q[1:]
+    idx = np.searchsorted(key, pk)
+    assert np.all(idx < len(key)) and np.array_equal(key[np.minimum(idx, len(key) - 1)], pk)
+
+
+def test_hand_example(mc):
+    gold = read_golden("hand_example.txt")
+    g = synth.from_edges(gold["n"][0][0], [tuple(e) for e in gold["edge"]], gold["accepting"][0])
+    csr = mc.build_csr(g.n, g.src, g.dst, transposed=False)
+    for w, init, s, c, *path in gold["lasso"]:
+        got = check(mc, g, csr, w, init, exact_path=True)
+        assert (got.stem_len, got.cycle_len, got.path.tolist()) == (s, c, path)
+    for w, init in gold["lasso_none"]:
+        assert check(mc, g, csr, w, init).status == mc.MAP_ENOPATH
+
+
+@pytest.mark.parametrize("L", [1, 2, 5, 64, 3000])
+def test_relabelled_cycle_with_chain(mc, L):
+    rng = np.random.default_rng(L)
+    chain = 700
+    n = L + chain
+    ids = rng.permutation(np.arange(1, n + 1))
+    cyc, tail = ids[:L].tolist(), ids[L:].tolist()
+    edges = [(cyc[i], cyc[(i + 1) % L]) for i in range(L)]
+    edges += [(tail[i], tail[i + 1]) for i in range(chain - 1)] + [(tail[-1], cyc[0])]
+    g = synth.from_edges(n, edges, [], name=f"cycle{L}+chain{chain}")
+    csr = mc.build_csr(g.n, g.src, g.dst, transposed=False)
+    for w in (cyc[0], cyc[L // 2], cyc[-1]):
+        check(mc, g, csr, w, 0, exact_path=True)
+    check(mc, g, csr, cyc[0], tail[0], exact_path=True)
+    check(mc, g, csr, tail[3], 0)            # chain vertex: no cycle
+    check(mc, g, csr, tail[0], cyc[0])       # the cycle does not reach the chain
+
+
+def test_self_loop_single_vertex_and_init_equal_witness(mc):
+    g = synth.from_edges(1, [(1, 1)], [1], name="selfloop1")
+    csr = mc.build_csr(g.n, g.src, g.dst, transposed=False)
+    got = check(mc, g, csr, 1, 0, exact_path=True)
+    assert got.path.tolist() == [1, 1]
+    g = synth.from_edges(4, [(1, 2), (2, 2), (2, 3), (4, 4)], [2], name="selfloops")
+    csr = mc.build_csr(g.n, g.src, g.dst, transposed=False)
+    check(mc, g, csr, 2, 1, exact_path=True)
+    check(mc, g, csr, 2, 2, exact_path=True)
+    check(mc, g, csr, 2, 4)                  # 4 only reaches itself
+    check(mc, g, csr, 3, 0)                  # sink
+
+
+def test_capacity(mc):
+    g = synth.from_edges(3, [(1, 2), (2, 3), (3, 1)], [], name="tri")
+    csr = mc.build_csr(g.n, g.src, g.dst, transposed=False)
+    got = check(mc, g, csr, 1, 0, cap=3)
+    assert got.status == mc.MAP_ENOSPC and got.path is None
+    check(mc, g, csr, 1, 0, cap=4, exact_path=True)
+    check(mc, g, csr, 1, 2, cap=4)           # stem 2->3->1 (2) + cycle (3) needs 6
+    check(mc, g, csr, 1, 2, cap=6, exact_path=True)
+
+
+def _random_digraph(seed, n, deg):
+    rng = np.random.default_rng(seed)
+    m = n * deg
+    src = rng.integers(1, n + 1, m).astype(np.int32)
+    dst = rng.integers(1, n + 1, m).astype(np.int32)
+    return synth.Graph(n=n, src=src, dst=dst, acc=np.zeros(n, np.uint8), name=f"rand{seed}_{n}_{deg}")
+
+
+@pytest.mark.parametrize("seed,n,deg", [(1, 60, 1), (2, 500, 1), (3, 5000, 1), (4, 20000, 1), (5, 70000, 2)])
+def test_random_digraphs(mc, seed, n, deg):
+    # out-degree around 1: long shortest cycles, many vertices on none
+    g = _random_digraph(seed, n, deg)
+    csr = mc.build_csr(g.n, g.src, g.dst, transposed=False)
+    rng = np.random.default_rng(seed)
+    for w in rng.integers(1, n + 1, 6).tolist():
+        for init in (0, int(rng.integers(1, n + 1)), 1):
+            check(mc, g, csr, w, init)
+
+
+def test_config1_witness(mc):
+    g = synth.config1()
+    ref = oracle.map_detect(g)
+    assert ref.found == 1
+    csr = mc.build_csr(g.n, g.src, g.dst, transposed=False)
+    for init in (0, 1, g.n, 4321):
+        check(mc, g, csr, ref.witness, init)
+
+
+def test_dag_has_no_lasso(mc):
+    g = synth.config3(n=1 << 14)
+    csr = mc.build_csr(g.n, g.src, g.dst, transposed=False)
+    for w in (1, 77, g.n):
+        got = check(mc, g, csr, w, 0)
+        assert got.status == mc.MAP_ENOPATH and got.stem_len == 0 and got.cycle_len == -1
+
+
+def test_bad_column_reported(mc):
+    import torch
+    # row 0 -> {1, 7}: 7 is outside 0..2
+    row_ptr = torch.tensor([0, 2, 3, 4], dtype=torch.int32, device="cuda")
+    col = torch.tensor([1, 7, 2, 0], dtype=torch.int32, device="cuda")
+    ws = mc.workspace(3, 4)
+    path = torch.zeros(16, dtype=torch.int32, device="cuda")
+    res = torch.zeros(8, dtype=torch.int32, device="cuda")
+    assert mc.map_lasso(3, row_ptr, col, 1, 0, path, res, ws) == mc.MAP_OK
+    assert int(res[0].item()) == mc.MAP_ERANGE_DEV
+
+
+@pytest.mark.parametrize("planted_seed,n", [(3, 1 << 15), (2, 1 << 20)])
+def test_config2A_witness(mc, planted_seed, n):
+    g = synth.config2(seed=planted_seed, n=n, planted=True)
+    if n == 1 << 20:
+        gold = json.load(open(os.path.join(ROOT, "tests", "golden", "full_size.json")))["c2A"]
+        w = gold["witness"]
+    else:
+        w = oracle.map_detect(g).witness
+    assert w > 0
+    csr = mc.build_csr(g.n, g.src, g.dst, transposed=False)
+    for init in (0, 1, max(1, w - 5000)):
+        got = check(mc, g, csr, w, init)
+        say("  stem", got.stem_len, "cycle", got.cycle_len, "levels", got.levels, "edges", got.edges_scanned)
