@@ -22,6 +22,9 @@ tarjan(g)               accepting-cycle verdict from strongly connected componen
 ndfs(g)                 accepting-cycle verdict from nested depth-first search
 lasso(g, w, init)       counterexample: shortest path init -> w, then shortest
                         cycle through w (breadth-first search over successors)
+trim(g)                 relevance pruning: vertices left after repeatedly
+                        removing those with no remaining predecessor or
+                        successor, and the accepting flags restricted to them
 """
 from __future__ import annotations
 
@@ -76,6 +79,8 @@ def _load():
         lib.oracle_lasso.argtypes = [i32, i64, _i32p, _i32p, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                      vp, i32]
         lib.oracle_lasso.restype = ctypes.c_int
+        lib.oracle_trim.argtypes = [i32, i64, _i32p, _i32p, _u8p, _u8p, _u8p]
+        lib.oracle_trim.restype = i64
         _lib = lib
     return _lib
 
@@ -194,3 +199,14 @@ def lasso(g, w: int, init: int = 0, cap: int | None = None) -> Lasso:
     status = {0: "ok", -8: "no_path", -9: "no_space"}[rc]
     s, c = int(s_len.value), int(c_len.value)
     return Lasso(status, s, c, path[:s + c + 1].copy() if rc == 0 else None)
+
+
+def trim(g, acc=None):
+    """(keep uint8[n], accepting flags & keep) after trimming cycle-free vertices."""
+    src, dst, a = _arrays(g, acc)
+    keep = np.zeros(g.n, np.uint8)
+    acc_out = np.zeros(g.n, np.uint8)
+    k = int(_load().oracle_trim(g.n, len(src), src, dst, a, keep, acc_out))
+    if k < 0:
+        raise ValueError(f"oracle_trim failed rc={k}")
+    return keep, acc_out

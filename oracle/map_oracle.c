@@ -532,3 +532,67 @@ out:
     adj_free(&s);
     return rc;
 }
+
+/* --------------------------------------------------------- pruning --- */
+/*
+ * Relevance pruning for detection on a growing graph.  The paper's tool keeps
+ * in its matrix only the states of components that contain accepting states,
+ * and a second thread repeatedly runs the detection on the part of the graph
+ * built so far (Section 2).  That component reduction needs the property
+ * automaton; its stand-in on a bare graph is the trim of cycle-free vertices:
+ * while some vertex has no remaining predecessor or no remaining successor,
+ * remove it.  What remains is the largest vertex set in which every vertex has
+ * a predecessor and a successor inside the set.  Every cycle lies inside it,
+ * so clearing the accepting flag of every vertex outside it leaves the
+ * verdict unchanged (K and the witness follow the reduced accepting set).
+ *
+ * keep[i] = 1 if id i+1 remains; acc_out (may be NULL) = acc & keep.
+ * Queue-based peeling with per-vertex counts of remaining in- and out-edges
+ * (parallel edges counted with multiplicity), O(n + m).  Returns the number of
+ * vertices kept, or a negative error.
+ */
+int64_t oracle_trim(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const uint8_t *acc,
+                    uint8_t *keep, uint8_t *acc_out) {
+    int rc = check_ids(n, m, src, dst);
+    if (rc) return rc;
+    if (!keep) return OR_EINVAL;
+    adj_t s, p;
+    rc = adj_build(n, m, src, dst, 1, &s);
+    if (rc) return rc;
+    rc = adj_build(n, m, src, dst, 0, &p);
+    if (rc) { adj_free(&s); return rc; }
+    int64_t *indeg = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    int64_t *outdeg = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    int32_t *queue = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    int64_t kept = 0;
+    if (!indeg || !outdeg || !queue) { kept = OR_ENOMEM; goto out; }
+    int64_t head = 0, tail = 0;
+    for (int32_t v = 1; v <= n; ++v) {
+        indeg[v] = p.off[v + 1] - p.off[v];
+        outdeg[v] = s.off[v + 1] - s.off[v];
+        keep[v - 1] = 1;
+        if (indeg[v] == 0 || outdeg[v] == 0) { keep[v - 1] = 0; queue[tail++] = v; }
+    }
+    while (head < tail) {
+        int32_t v = queue[head++];
+        for (int64_t j = s.off[v]; j < s.off[v + 1]; ++j) {      /* v's out-edges leave */
+            int32_t w = s.nb[j];
+            if (--indeg[w] == 0 && keep[w - 1]) { keep[w - 1] = 0; queue[tail++] = w; }
+        }
+        for (int64_t j = p.off[v]; j < p.off[v + 1]; ++j) {      /* v's in-edges leave */
+            int32_t u = p.nb[j];
+            if (--outdeg[u] == 0 && keep[u - 1]) { keep[u - 1] = 0; queue[tail++] = u; }
+        }
+    }
+    for (int32_t v = 1; v <= n; ++v) {
+        kept += keep[v - 1];
+        if (acc_out) acc_out[v - 1] = (uint8_t)(acc && acc[v - 1] && keep[v - 1] ? 1 : 0);
+    }
+out:
+    free(indeg);
+    free(outdeg);
+    free(queue);
+    adj_free(&s);
+    adj_free(&p);
+    return kept;
+}
