@@ -185,6 +185,39 @@ int map_lasso(int32_t n, const int32_t *row_ptr, const int32_t *col, int32_t wit
               int32_t *path, int32_t path_cap, map_lasso_result *result, void *ws, size_t ws_bytes,
               void *stream);
 
+/* Result of map_trim (device memory, 16 bytes). */
+typedef struct map_trim_result {
+  int32_t status;         /* MAP_OK, MAP_ERANGE_DEV (a CSR entry outside 0..n-1), MAP_EDEVICE */
+  int32_t kept;           /* vertices kept */
+  int32_t accepting_kept; /* accepting vertices kept (0 without accepting flags) */
+  int32_t rounds;         /* peeling rounds after the first frontier */
+} map_trim_result;
+
+/*
+ * Relevance pruning before detection.  The paper's tool keeps in its matrix
+ * only the states of components that contain accepting states and runs the
+ * detection repeatedly on the part of the graph built so far (Section 2); that
+ * reduction needs the property automaton.  Its stand-in on a bare graph:
+ * remove, while one exists, a vertex with no remaining predecessor or no
+ * remaining successor.  The vertices left form the largest set in which every
+ * vertex has a predecessor and a successor inside the set; every cycle lies in
+ * it, so MAP on accepting & keep gives the same verdict as on accepting (K and
+ * the witness follow the reduced accepting set).  One cooperative launch,
+ * peeling in rounds with a grid barrier each.
+ *   row_ptr, col      device pull CSR of G (row v = successors), from map_build_csr.
+ *   rrow_ptr, rcol    device transposed CSR (row v = predecessors), from map_build_csr.
+ *   accepting         device uint8[n] or NULL; accepting_out device uint8[n] out
+ *                     (accepting & keep), NULL exactly when accepting is.
+ *   keep_out          device uint8[n] out: 1 if the vertex is kept.
+ *   result            device map_trim_result out.
+ *   ws                workspace of at least map_workspace_bytes(n, m, 0) bytes.
+ * Host errors: MAP_ERANGE (n), MAP_EINVAL (null pointer, or only one of
+ * accepting / accepting_out), MAP_ENOSPC (workspace).
+ */
+int map_trim(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *rrow_ptr, const int32_t *rcol,
+             const uint8_t *accepting, uint8_t *keep_out, uint8_t *accepting_out, map_trim_result *result,
+             void *ws, size_t ws_bytes, void *stream);
+
 /* One graph of a batch (device memory; see map_detect_batch). */
 typedef struct map_graph_desc {
   int32_t n;                  /* vertices, ids 1..n */

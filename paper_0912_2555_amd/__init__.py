@@ -12,8 +12,9 @@ The raw calls mirror the C names and never synchronize:
 ``map_propagate(n, row_ptr, col, rrow_ptr, rcol, accepting, map_out, result, flags, ws)``
 ``map_detect(n, row_ptr, col, rrow_ptr, rcol, accepting0, result, trace, accepting_out, max_iterations, flags, ws)``
 ``map_lasso(n, row_ptr, col, witness, init, path, result, ws)``
+``map_trim(n, row_ptr, col, rrow_ptr, rcol, accepting, keep_out, accepting_out, result, ws)``
 
-Convenience wrappers (``Csr``, ``build_csr``, ``propagate``, ``detect``, ``lasso``)
+Convenience wrappers (``Csr``, ``build_csr``, ``propagate``, ``detect``, ``lasso``, ``trim``)
 allocate the tensors, call the raw entry points and synchronize when results
 are read back.
 
@@ -51,7 +52,7 @@ MAP_FLAG_PUSH = 0x10
 EXPORTS = ("map_workspace_bytes", "map_build_csr", "map_propagate", "map_detect", "map_batch_workspace_bytes",
            "map_detect_batch", "map_job_scratch_bytes", "map_engine_create", "map_engine_workgroups",
            "map_engine_submit", "map_engine_poll", "map_engine_stop", "map_engine_destroy", "map_lasso",
-           "map_strerror")
+           "map_trim", "map_strerror")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_0912_2555_amd.build` "
@@ -69,6 +70,8 @@ _lib.map_detect.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, 
 _lib.map_detect.restype = ctypes.c_int
 _lib.map_lasso.argtypes = [_i32, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _sz, _vp]
 _lib.map_lasso.restype = ctypes.c_int
+_lib.map_trim.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.map_trim.restype = ctypes.c_int
 _lib.map_batch_workspace_bytes.argtypes = [_i32, _i64, _u32]
 _lib.map_batch_workspace_bytes.restype = _sz
 _lib.map_detect_batch.argtypes = [_i32, _vp, _vp, _vp, _i64, _u32, _vp, _sz, _vp]
@@ -165,6 +168,12 @@ def map_lasso(n, row_ptr, col, witness, init, path, result, ws, stream=None) -> 
     cap = 0 if path is None else int(path.numel())
     return _lib.map_lasso(n, _ptr(row_ptr), _ptr(col), witness, init, _ptr(path), cap, _ptr(result), _ptr(ws),
                           0 if ws is None else ws.numel() * ws.element_size(), _stream(stream))
+
+
+def map_trim(n, row_ptr, col, rrow_ptr, rcol, accepting, keep_out, accepting_out, result, ws, stream=None) -> int:
+    return _lib.map_trim(n, _ptr(row_ptr), _ptr(col), _ptr(rrow_ptr), _ptr(rcol), _ptr(accepting), _ptr(keep_out),
+                         _ptr(accepting_out), _ptr(result), _ptr(ws),
+                         0 if ws is None else ws.numel() * ws.element_size(), _stream(stream))
 
 
 def map_batch_workspace_bytes(count: int, total_n: int, flags: int = 0) -> int:
@@ -301,6 +310,35 @@ def lasso(csr: Csr, witness: int, init: int = 0, cap: int | None = None, ws=None
     status, s, c, plen = (int(x) for x in a[:4])
     scanned = int(a[4:6].view(np.int64)[0])
     return LassoOut(status, s, c, path[:plen].cpu().numpy() if status == MAP_OK else None, scanned, int(a[6]))
+
+
+@dataclass
+class TrimOut:
+    status: int
+    kept: int
+    accepting_kept: int
+    rounds: int
+    keep: torch.Tensor                 # device uint8[n]
+    accepting: torch.Tensor | None     # device uint8[n]: accepting & keep
+
+
+def trim(csr: Csr, accepting=None, ws=None, stream=None, sync: bool = True) -> TrimOut:
+    """Relevance pruning on the device (needs the transposed CSR); synchronizes to read the counts."""
+    if csr.rrow_ptr is None:
+        raise ValueError("trim needs the transposed CSR (build_csr(..., transposed=True))")
+    dev = csr.row_ptr.device
+    acc = None if accepting is None else torch.as_tensor(accepting, dtype=torch.uint8).to(dev).contiguous()
+    keep = torch.empty(csr.n, dtype=torch.uint8, device=dev)
+    acc_out = torch.empty(csr.n, dtype=torch.uint8, device=dev) if acc is not None else None
+    res = torch.zeros(4, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = workspace(csr.n, csr.m, device=dev)
+    _check(map_trim(csr.n, csr.row_ptr, csr.col, csr.rrow_ptr, csr.rcol, acc, keep, acc_out, res, ws, stream),
+           "map_trim")
+    if not sync:
+        return TrimOut(0, -1, -1, -1, keep, acc_out)
+    a = res.cpu().numpy()
+    return TrimOut(int(a[0]), int(a[1]), int(a[2]), int(a[3]), keep, acc_out)
 
 
 # ------------------------------------------------------------------ batches

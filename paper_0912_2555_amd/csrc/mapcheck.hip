@@ -102,9 +102,11 @@ struct alignas(256) CtrlT {
   uint32_t pad2[31];
   alignas(128) uint32_t fcount[2];  // push and lasso: entries appended to frontier 0 / 1
   uint32_t hit;                     // lasso: 1 + the vertex whose edge reached the target
-  uint32_t bad;                     // lasso: an edge endpoint outside 0..n-1 was read
+  uint32_t bad;                     // lasso and trim: an edge endpoint outside 0..n-1 was read
   unsigned long long scanned;       // lasso: edges examined
-  uint32_t pad3[26];
+  uint32_t kept;                    // trim: vertices kept
+  uint32_t acc_kept;                // trim: accepting vertices kept
+  uint32_t pad3[24];
   unsigned long long quiet[Q];
 };
 using Ctrl = CtrlT<kMaxBlocks>;
@@ -1435,6 +1437,144 @@ aborted:
   }
 }
 
+// ---------------------------------------------------------------- pruning --
+
+// Arguments of the trim of cycle-free vertices.
+struct TrimArgs {
+  int32_t n;
+  const int32_t* row_ptr;  // pull CSR of G: row v = successors
+  const int32_t* col;
+  const int32_t* rrow_ptr; // transposed CSR: row v = predecessors
+  const int32_t* rcol;
+  const uint8_t* acc_in;   // or nullptr
+  uint8_t* keep_out;
+  uint8_t* acc_out;        // or nullptr
+  map_trim_result* result;
+  uint32_t* indeg;         // [n] in-edges from vertices not removed
+  uint32_t* outdeg;        // [n] out-edges to vertices not removed
+  uint32_t* removed;       // [n] 1 once removed (claimed by compare-and-swap)
+  int32_t* front[2];
+  Ctrl* ctrl;
+};
+
+// Removes, while one exists, a vertex with no remaining predecessor or no
+// remaining successor (parallel edges counted with multiplicity), in rounds:
+// the first frontier is every vertex with no in-edge or no out-edge; a round
+// takes a frontier of removed vertices, subtracts each one's out-edges from
+// its successors' in-counts and its in-edges from its predecessors'
+// out-counts, and a vertex whose count reaches 0 is claimed (compare-and-swap
+// on its removed word) and appended to the next frontier.  A grid barrier
+// ends each round and carries the next frontier's size.  A vertex on a cycle
+// always keeps an in-edge and an out-edge from the cycle, so it is never
+// removed.
+__global__ void __launch_bounds__(kBlock) map_trim_kernel(TrimArgs a) {
+  Grid<Ctrl> g;
+  g.c = a.ctrl;
+  g.gen = 0;
+  g.nblocks = gridDim.x;
+  g.ngroups = min((int)gridDim.x, kMaxGroups);
+  g.group = blockIdx.x % g.ngroups;
+  g.group_size = gridDim.x / g.ngroups + ((blockIdx.x % g.ngroups) < (gridDim.x % g.ngroups) ? 1 : 0);
+  g.rank = blockIdx.x;
+  Ctrl* c = a.ctrl;
+  const int lane = threadIdx.x & (kWave - 1), wib = threadIdx.x / kWave;
+  const int64_t gw = (int64_t)g.rank * kWavesPerBlock + wib, nw = (int64_t)g.nblocks * kWavesPerBlock;
+  const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+  int32_t rounds = 0;
+  uint32_t napp = 0, size = 0, kept = 0, acc_kept = 0;
+  int fc = 0;
+  // Counts, and the first frontier into front[0] (counter fcount[0], zero).
+  for (int64_t v0 = gw * kWave; v0 < a.n; v0 += nw * kWave) {
+    const int64_t v = v0 + lane;
+    bool take = false;
+    if (v < a.n) {
+      const uint32_t in = (uint32_t)(a.rrow_ptr[v + 1] - a.rrow_ptr[v]);
+      const uint32_t out = (uint32_t)(a.row_ptr[v + 1] - a.row_ptr[v]);
+      a.indeg[v] = in;
+      a.outdeg[v] = out;
+      take = in == 0 || out == 0;
+      a.removed[v] = take ? 1u : 0u;
+    }
+    napp += frontier_append(a.front[0], &c->fcount[0], take, (int32_t)v, lane);
+  }
+  if (!grid_sync(g, lasso_block_sum(napp), &size)) goto aborted;
+  while (size > 0) {
+    // Frontier fc is read and fc ^ 1 appended to (its counter is zero: it was
+    // cleared in the round that read it, before the barrier that closed it).
+    if (g.rank == 0 && threadIdx.x == 0) st_agent(&c->fcount[fc], 0u);
+    const int32_t* F = a.front[fc];
+    int32_t* Fn = a.front[fc ^ 1];
+    uint32_t* cn = &c->fcount[fc ^ 1];
+    napp = 0;
+    for (int64_t i0 = gw * kWave; i0 < (int64_t)size; i0 += nw * kWave) {
+      const int64_t i = i0 + lane;
+      int32_t k = 0, k1 = 0, r = 0, r1 = 0;
+      if (i < (int64_t)size) {
+        const int32_t v = F[i];
+        if ((uint32_t)v < (uint32_t)a.n) {
+          k = a.row_ptr[v];
+          k1 = a.row_ptr[v + 1];
+          r = a.rrow_ptr[v];
+          r1 = a.rrow_ptr[v + 1];
+        } else {
+          st_agent(&c->bad, 1u);
+        }
+      }
+      // Out-edges first, then in-edges; one edge per lane per step.
+      for (;;) {
+        const bool out_e = k < k1, in_e = !out_e && r < r1;
+        if (__ballot(out_e || in_e) == 0) break;
+        bool take = false;
+        int32_t x = 0;
+        if (out_e || in_e) {
+          x = out_e ? a.col[k++] : a.rcol[r++];
+          if ((uint32_t)x >= (uint32_t)a.n) {
+            st_agent(&c->bad, 1u);
+          } else {
+            uint32_t* cnt = out_e ? &a.indeg[x] : &a.outdeg[x];
+            if (__hip_atomic_fetch_sub(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1u) {
+              uint32_t zero = 0;
+              take = __hip_atomic_compare_exchange_strong(&a.removed[x], &zero, 1u, __ATOMIC_RELAXED,
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+          }
+        }
+        napp += frontier_append(Fn, cn, take, x, lane);
+      }
+    }
+    if (!grid_sync(g, lasso_block_sum(napp), &size)) goto aborted;
+    ++rounds;
+    fc ^= 1;
+  }
+  // Outputs and counts.
+  for (int64_t v = (int64_t)g.rank * kBlock + threadIdx.x; v < a.n; v += (int64_t)g.nblocks * kBlock) {
+    const uint32_t keep = ld_agent(&a.removed[v]) ? 0u : 1u;
+    a.keep_out[v] = (uint8_t)keep;
+    kept += keep;
+    if (a.acc_out) {
+      const uint32_t ak = keep && a.acc_in[v] ? 1u : 0u;
+      a.acc_out[v] = (uint8_t)ak;
+      acc_kept += ak;
+    }
+  }
+  kept = wave_sum_u32(kept);
+  acc_kept = wave_sum_u32(acc_kept);
+  if (lane == 0) {
+    if (kept) __hip_atomic_fetch_add(&c->kept, kept, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (acc_kept) __hip_atomic_fetch_add(&c->acc_kept, acc_kept, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (!grid_sync(g, 0, nullptr)) goto aborted;
+  if (leader) {
+    a.result->status = ld_agent(&c->bad) ? MAP_ERANGE_DEV : MAP_OK;
+    a.result->kept = (int32_t)ld_agent(&c->kept);
+    a.result->accepting_kept = (int32_t)ld_agent(&c->acc_kept);
+    a.result->rounds = rounds;
+  }
+  return;
+aborted:
+  if (leader) a.result->status = MAP_EDEVICE;
+}
+
 // Loop arguments of one graph solved by a gang: scratch holds the packed
 // values (4n bytes, 256-aligned) followed by the working accepting flags.
 __device__ LoopArgs gang_args(int32_t n, const int32_t* row_ptr, const int32_t* col, const uint8_t* acc0,
@@ -2056,7 +2196,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 bool sizes_ok(int32_t n, int64_t m) { return n >= 1 && n <= 0x7ffffffe && m >= 0 && m <= 0x7fffffff; }
 
 struct Layout {
-  size_t ctrl, pv, accw, front0, front1, mark, cursor, sums, total;
+  size_t ctrl, pv, accw, front0, front1, mark, aux, cursor, sums, total;
 };
 
 Layout layout(int32_t n) {
@@ -2076,6 +2216,9 @@ Layout layout(int32_t n) {
   L.front1 = off;
   off += align256((size_t)n * 4);
   L.mark = off;
+  off += align256((size_t)n * 4);
+  // pruning: removed flags
+  L.aux = off;
   off += align256((size_t)n * 4);
   size_t end_loop = off;
   // CSR build (shares the region after ctrl)
@@ -2419,6 +2562,75 @@ int map_lasso(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t wit
   if (hipGetLastError() != hipSuccess) return MAP_EDEVICE;
   void* args[] = {&a};
   if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(map_lasso_kernel), dim3((unsigned)grid), dim3(kBlock),
+                                 args, 0, st) != hipSuccess)
+    return MAP_EDEVICE;
+  return MAP_OK;
+}
+
+int map_trim(int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* rrow_ptr, const int32_t* rcol,
+             const uint8_t* accepting, uint8_t* keep_out, uint8_t* accepting_out, map_trim_result* result, void* ws,
+             size_t ws_bytes, void* stream) {
+  if (n < 1 || n > 0x7ffffffe) return MAP_ERANGE;
+  if (!row_ptr || !col || !rrow_ptr || !rcol || !keep_out || !result || !ws) return MAP_EINVAL;
+  if ((accepting == nullptr) != (accepting_out == nullptr)) return MAP_EINVAL;
+  const Layout L = layout(n);
+  if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return MAP_ENOSPC;
+  static std::mutex mu;
+  static int cache_cus[64], cache_per[64], cache_coop[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return MAP_EDEVICE;
+  int cus, per, coop;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (cache_cus[dev] == 0) {
+      int c = 0, nb = 0, co = 0;
+      if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return MAP_EDEVICE;
+      if (hipDeviceGetAttribute(&co, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) return MAP_EDEVICE;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(map_trim_kernel), kBlock,
+                                                       0) != hipSuccess)
+        return MAP_EDEVICE;
+      if (c <= 0 || nb <= 0) return MAP_EDEVICE;
+      cache_cus[dev] = c;
+      cache_per[dev] = nb;
+      cache_coop[dev] = co;
+    }
+    cus = cache_cus[dev];
+    per = cache_per[dev];
+    coop = cache_coop[dev];
+  }
+  if (!coop) return MAP_EDEVICE;
+  // About one workgroup per 4096 vertices, at most one per CU (the rounds
+  // usually hold far fewer vertices than the graph; fewer workgroups make the
+  // per-round barrier cheaper).
+  int64_t grid = ((int64_t)n + 4095) / 4096;
+  if (grid > (int64_t)cus * per) grid = (int64_t)cus * per;
+  if (grid > cus) grid = cus;
+  if (grid > kMaxBlocks) grid = kMaxBlocks;
+  if (grid >= kMaxGroups) grid -= grid % kMaxGroups;
+  if (grid < 1) grid = 1;
+  char* w = static_cast<char*>(ws);
+  TrimArgs a;
+  a.n = n;
+  a.row_ptr = row_ptr;
+  a.col = col;
+  a.rrow_ptr = rrow_ptr;
+  a.rcol = rcol;
+  a.acc_in = accepting;
+  a.keep_out = keep_out;
+  a.acc_out = accepting_out;
+  a.result = result;
+  a.indeg = reinterpret_cast<uint32_t*>(w + L.pv);
+  a.outdeg = reinterpret_cast<uint32_t*>(w + L.mark);
+  a.removed = reinterpret_cast<uint32_t*>(w + L.aux);
+  a.front[0] = reinterpret_cast<int32_t*>(w + L.front0);
+  a.front[1] = reinterpret_cast<int32_t*>(w + L.front1);
+  a.ctrl = reinterpret_cast<Ctrl*>(w + L.ctrl);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(fill_u32, dim3(8), dim3(256), 0, st, reinterpret_cast<uint32_t*>(a.ctrl),
+                     (int64_t)(kCtrlBytes / 4), 0u);
+  if (hipGetLastError() != hipSuccess) return MAP_EDEVICE;
+  void* args[] = {&a};
+  if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(map_trim_kernel), dim3((unsigned)grid), dim3(kBlock),
                                  args, 0, st) != hipSuccess)
     return MAP_EDEVICE;
   return MAP_OK;

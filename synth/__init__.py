@@ -176,3 +176,17 @@ def random_graph(seed: int, n: int, m: int, p_acc: float = 0.2, self_loops: bool
         src, dst = src[keep], dst[keep]
     acc = (rng.random(n) < p_acc).astype(np.uint8)
     return Graph(n=n, src=src, dst=dst, acc=acc, name=f"rand(n={n},m={m},seed={seed})")
+
+
+def generation_order(g: Graph) -> Graph:
+    """The same graph with its edges in the order a breadth-first state generator emits them: grouped by
+    source id, ascending (stable within a source).  Generated edge lists are already grouped that way except
+    for edges appended afterwards (the planted cycle), which this moves to their source's place."""
+    order = np.argsort(g.src, kind="stable")
+    return Graph(n=g.n, src=g.src[order].copy(), dst=g.dst[order].copy(), acc=g.acc.copy(),
+                 name=g.name + "/gen-order", planted=list(g.planted))
+
+
+def prefix(g: Graph, m: int) -> Graph:
+    """The graph of the first m edges (all n vertices, same accepting flags)."""
+    return Graph(n=g.n, src=g.src[:m].copy(), dst=g.dst[:m].copy(), acc=g.acc.copy(), name=f"{g.name}[:{m}]")

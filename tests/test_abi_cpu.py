@@ -40,7 +40,7 @@ def test_exports_every_declared_symbol(lib):
     assert names == ["map_batch_workspace_bytes", "map_build_csr", "map_detect", "map_detect_batch",
                      "map_engine_create", "map_engine_destroy", "map_engine_poll", "map_engine_stop",
                      "map_engine_submit", "map_engine_workgroups", "map_job_scratch_bytes", "map_lasso",
-                     "map_propagate", "map_strerror", "map_workspace_bytes"]
+                     "map_propagate", "map_strerror", "map_trim", "map_workspace_bytes"]
     for name in names:
         assert hasattr(lib, name), name
 
@@ -52,8 +52,9 @@ def test_header_compiles_as_c():
         src = os.path.join(d, "t.c")
         with open(src, "w") as f:
             f.write('#include "mapcheck.h"\nint main(void){ map_result r; map_job j; map_lasso_result l; '
-                    '(void)r; (void)j; (void)l; return (int)sizeof(map_result) - 32 + (int)sizeof(map_job) - 72 '
-                    '+ (int)sizeof(map_lasso_result) - 32; }\n')
+                    'map_trim_result t; (void)r; (void)j; (void)l; (void)t; '
+                    'return (int)sizeof(map_result) - 32 + (int)sizeof(map_job) - 72 '
+                    '+ (int)sizeof(map_lasso_result) - 32 + (int)sizeof(map_trim_result) - 16; }\n')
         subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
                                "-o", os.path.join(d, "t"), src])
         assert subprocess.call([os.path.join(d, "t")]) == 0
@@ -110,6 +111,20 @@ def test_lasso_host_side_errors_without_device(lib):
     assert lib.map_lasso(5, fake, fake, 2, 0, fake, 8, fake, fake, 16, None) == MAP_ENOSPC
     assert lib.map_lasso(5, fake, fake, 2, 0, fake, 8, fake, ctypes.c_void_p(0x1004), big, None) == MAP_ENOSPC
     assert lib.map_strerror(-8).decode().startswith("no path")
+
+
+def test_trim_host_side_errors_without_device(lib):
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    lib.map_trim.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    f = ctypes.c_void_p(0x1000)
+    big = lib.map_workspace_bytes(5, 3, 0)
+    assert lib.map_trim(0, f, f, f, f, None, f, None, f, f, big, None) == MAP_ERANGE
+    assert lib.map_trim(5, f, f, None, f, None, f, None, f, f, big, None) == MAP_EINVAL     # no transposed CSR
+    assert lib.map_trim(5, f, f, f, f, None, None, None, f, f, big, None) == MAP_EINVAL     # keep_out NULL
+    assert lib.map_trim(5, f, f, f, f, f, f, None, f, f, big, None) == MAP_EINVAL          # accepting w/o out
+    assert lib.map_trim(5, f, f, f, f, None, f, f, f, f, big, None) == MAP_EINVAL          # out w/o accepting
+    assert lib.map_trim(5, f, f, f, f, None, f, None, None, f, big, None) == MAP_EINVAL    # result NULL
+    assert lib.map_trim(5, f, f, f, f, None, f, None, f, f, 64, None) == MAP_ENOSPC
 
 
 def test_strerror(lib):
