@@ -1260,6 +1260,52 @@ __device__ uint32_t lasso_block_sum(uint32_t x) {
   return t;
 }
 
+// Flattened frontier expansion, shared by the counterexample search and the
+// pruning.  A wave takes 64 frontier vertices at a time; an inclusive scan of
+// their degrees across the wave gives each vertex the first slot of its edges
+// in the wave's combined list, and lane l examines slots q0 + l + 64 s (s <
+// kExpandPerLane) of that list.  The wave thus issues the reads and atomics of
+// up to 64 * kExpandPerLane edges together, instead of one edge per lane per
+// step, and appends what it claimed with one counter update per chunk.
+constexpr int kExpandPerLane = 4;
+
+// Lane of this wave whose slice of the combined list holds slot q: the last
+// lane whose first slot is <= q (binary search over the lanes with shuffles;
+// every lane of the wave must call it).
+__device__ __forceinline__ int slot_owner(uint32_t q, uint32_t first) {
+  int lo = 0;
+#pragma unroll
+  for (int step = kWave / 2; step > 0; step >>= 1) {
+    const uint32_t f = (uint32_t)__shfl((int)first, lo + step, kWave);
+    if (f <= q) lo += step;
+  }
+  return lo;
+}
+
+// Appends x[s] for every s with take[s] to frontier F with one counter update
+// for the whole wave; returns the number appended by the wave (wave-uniform).
+template <int N>
+__device__ __forceinline__ uint32_t frontier_append_n(int32_t* F, uint32_t* cnt, const bool* take, const int32_t* x,
+                                                      int lane) {
+  uint32_t c = 0;
+#pragma unroll
+  for (int s = 0; s < N; ++s) c += take[s] ? 1u : 0u;
+  uint32_t incl = c;
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)incl, off, kWave);
+    if (lane >= off) incl += y;
+  }
+  const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+  if (total == 0) return 0;
+  uint32_t base = 0;
+  if (lane == 0) base = __hip_atomic_fetch_add(cnt, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  base = (uint32_t)__shfl((int)base, 0, kWave) + (incl - c);
+#pragma unroll
+  for (int s = 0; s < N; ++s)
+    if (take[s]) F[base++] = x[s];
+  return total;
+}
+
 // Breadth-first search from `from` until an edge enters `to`, run by every
 // thread of the grid.  The start is marked reached (parent -1) but an edge
 // into `to` is taken before that mark is looked at, so from == to finds a
@@ -1303,37 +1349,69 @@ __device__ int32_t lasso_bfs(const LassoArgs& a, Grid<Ctrl>& g, int32_t from, in
     uint32_t napp = 0;
     for (int64_t i0 = gw * kWave; i0 < (int64_t)size; i0 += nw * kWave) {
       const int64_t i = i0 + lane;
-      int32_t u = 0, k = 0, k1 = 0;
+      int32_t u = 0, k = 0;
+      uint32_t deg = 0;
       if (i < (int64_t)size) {
         u = F[i];
         if ((uint32_t)u < (uint32_t)a.n) {
           k = a.row_ptr[u];
-          k1 = a.row_ptr[u + 1];
+          deg = (uint32_t)(a.row_ptr[u + 1] - k);
         } else {
           st_agent(&c->bad, 1u);
         }
       }
-      for (;;) {
-        const bool act = k < k1;
-        if (__ballot(act) == 0) break;
-        bool take = false;
-        int32_t v = 0;
-        if (act) {
-          v = a.col[k++];
+      uint32_t incl = deg;
+      for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, off, kWave);
+        if (lane >= off) incl += y;
+      }
+      const uint32_t first = incl - deg;
+      const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+      for (uint32_t q0 = 0; q0 < total; q0 += kWave * kExpandPerLane) {
+        int32_t v[kExpandPerLane], src[kExpandPerLane];
+        bool ok[kExpandPerLane], take[kExpandPerLane];
+        uint32_t pw[kExpandPerLane];
+#pragma unroll
+        for (int s = 0; s < kExpandPerLane; ++s) {
+          const uint32_t q = q0 + (uint32_t)(s * kWave + lane);
+          const int o = slot_owner(q, first);
+          const int32_t ko = __shfl(k, o, kWave);
+          const uint32_t fo = (uint32_t)__shfl((int)first, o, kWave);
+          src[s] = __shfl(u, o, kWave);
+          ok[s] = q < total;
+          v[s] = ok[s] ? a.col[ko + (int32_t)(q - fo)] : 0;
+        }
+        // Plain parent reads: a parent word only goes from 0 to nonzero during
+        // a search (the clear precedes a barrier), so nonzero is final; the
+        // compare-and-swap decides the claim.
+#pragma unroll
+        for (int s = 0; s < kExpandPerLane; ++s) {
+          pw[s] = 1u;
+          if (!ok[s]) continue;
           ++*scanned;
-          if ((uint32_t)v >= (uint32_t)a.n) {
+          if ((uint32_t)v[s] >= (uint32_t)a.n) {
             st_agent(&c->bad, 1u);
-          } else if (v == to) {
+            ok[s] = false;
+          } else if (v[s] == to) {
             uint32_t zero = 0;
-            __hip_atomic_compare_exchange_strong(&c->hit, &zero, (uint32_t)u + 1u, __ATOMIC_RELAXED,
+            __hip_atomic_compare_exchange_strong(&c->hit, &zero, (uint32_t)src[s] + 1u, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          } else if (ld_agent(&parent[v]) == 0u) {
-            uint32_t zero = 0;
-            take = __hip_atomic_compare_exchange_strong(&parent[v], &zero, (uint32_t)u + 1u, __ATOMIC_RELAXED,
-                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok[s] = false;
+          } else {
+            pw[s] = parent[v[s]];
           }
         }
-        napp += frontier_append(Fn, cn, take, v, lane);
+#pragma unroll
+        for (int s = 0; s < kExpandPerLane; ++s) {
+          take[s] = false;
+          if (ok[s] && pw[s] == 0u) {
+            uint32_t zero = 0;
+            take[s] = __hip_atomic_compare_exchange_strong(&parent[v[s]], &zero, (uint32_t)src[s] + 1u,
+                                                           __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+        napp += frontier_append_n<kExpandPerLane>(Fn, cn, take, v, lane);
       }
     }
     uint32_t tot = 0;
@@ -1508,38 +1586,66 @@ __global__ void __launch_bounds__(kBlock) map_trim_kernel(TrimArgs a) {
     napp = 0;
     for (int64_t i0 = gw * kWave; i0 < (int64_t)size; i0 += nw * kWave) {
       const int64_t i = i0 + lane;
-      int32_t k = 0, k1 = 0, r = 0, r1 = 0;
+      // A removed vertex's out-edges then its in-edges, flattened across the
+      // wave (slots [0, dout) of a vertex are col entries, the rest rcol).
+      int32_t k = 0, r = 0;
+      uint32_t dout = 0, deg = 0;
       if (i < (int64_t)size) {
         const int32_t v = F[i];
         if ((uint32_t)v < (uint32_t)a.n) {
           k = a.row_ptr[v];
-          k1 = a.row_ptr[v + 1];
           r = a.rrow_ptr[v];
-          r1 = a.rrow_ptr[v + 1];
+          dout = (uint32_t)(a.row_ptr[v + 1] - k);
+          deg = dout + (uint32_t)(a.rrow_ptr[v + 1] - r);
         } else {
           st_agent(&c->bad, 1u);
         }
       }
-      // Out-edges first, then in-edges; one edge per lane per step.
-      for (;;) {
-        const bool out_e = k < k1, in_e = !out_e && r < r1;
-        if (__ballot(out_e || in_e) == 0) break;
-        bool take = false;
-        int32_t x = 0;
-        if (out_e || in_e) {
-          x = out_e ? a.col[k++] : a.rcol[r++];
-          if ((uint32_t)x >= (uint32_t)a.n) {
+      uint32_t incl = deg;
+      for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, off, kWave);
+        if (lane >= off) incl += y;
+      }
+      const uint32_t first = incl - deg;
+      const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+      for (uint32_t q0 = 0; q0 < total; q0 += kWave * kExpandPerLane) {
+        int32_t x[kExpandPerLane];
+        bool ok[kExpandPerLane], out_e[kExpandPerLane], take[kExpandPerLane];
+        uint32_t old[kExpandPerLane];
+#pragma unroll
+        for (int s = 0; s < kExpandPerLane; ++s) {
+          const uint32_t q = q0 + (uint32_t)(s * kWave + lane);
+          const int o = slot_owner(q, first);
+          const int32_t ko = __shfl(k, o, kWave), ro = __shfl(r, o, kWave);
+          const uint32_t fo = (uint32_t)__shfl((int)first, o, kWave);
+          const uint32_t dout_o = (uint32_t)__shfl((int)dout, o, kWave);
+          const uint32_t j = q - fo;
+          ok[s] = q < total;
+          out_e[s] = j < dout_o;
+          x[s] = ok[s] ? (out_e[s] ? a.col[ko + (int32_t)j] : a.rcol[ro + (int32_t)(j - dout_o)]) : 0;
+        }
+#pragma unroll
+        for (int s = 0; s < kExpandPerLane; ++s) {
+          old[s] = 0u;
+          if (!ok[s]) continue;
+          if ((uint32_t)x[s] >= (uint32_t)a.n) {
             st_agent(&c->bad, 1u);
-          } else {
-            uint32_t* cnt = out_e ? &a.indeg[x] : &a.outdeg[x];
-            if (__hip_atomic_fetch_sub(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1u) {
-              uint32_t zero = 0;
-              take = __hip_atomic_compare_exchange_strong(&a.removed[x], &zero, 1u, __ATOMIC_RELAXED,
-                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+            ok[s] = false;
+            continue;
+          }
+          uint32_t* cnt = out_e[s] ? &a.indeg[x[s]] : &a.outdeg[x[s]];
+          old[s] = __hip_atomic_fetch_sub(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+#pragma unroll
+        for (int s = 0; s < kExpandPerLane; ++s) {
+          take[s] = false;
+          if (ok[s] && old[s] == 1u) {
+            uint32_t zero = 0;
+            take[s] = __hip_atomic_compare_exchange_strong(&a.removed[x[s]], &zero, 1u, __ATOMIC_RELAXED,
+                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
-        napp += frontier_append(Fn, cn, take, x, lane);
+        napp += frontier_append_n<kExpandPerLane>(Fn, cn, take, x, lane);
       }
     }
     if (!grid_sync(g, lasso_block_sum(napp), &size)) goto aborted;
