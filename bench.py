@@ -510,8 +510,8 @@ def main():
                     help="gang policy when serving: tune, one, or EDGES[+fit] (edges per workgroup)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(graphs shard by vertex range across GPUs only in the design notes)", file=sys.stderr)
+        print(f"bench.py: the detector runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding a graph by vertex range across GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     if args.calibrate_copy:
