@@ -66,6 +66,15 @@ extern "C" {
 #define MAP_FLAG_STREAM 0x4u /* never stage the CSR in on-chip memory: stream it every sweep */
 #define MAP_FLAG_SYNC_SWEEPS 0x8u /* a grid-wide barrier after every sweep (no asynchronous sweeps) */
 #define MAP_FLAG_PUSH 0x10u /* frontier sweeps over the transposed CSR (needs rrow_ptr, rcol) */
+/* map_detect, map_detect_batch, engine jobs: stop as soon as some vertex's
+ * value equals its own id during a propagation, not only at its fixpoint.
+ * Values during a propagation are genuine maximal accepting successors of
+ * subsets of the paths, so such a vertex lies on an accepting cycle: the
+ * verdict is the same as without the flag, but K can be smaller and the
+ * witness (a vertex on an accepting cycle, accepting in A_1) depends on the
+ * schedule.  Ignored by map_propagate; MAP_EINVAL together with MAP_FLAG_PUSH
+ * (unless MAP_FLAG_DENSE_ONLY is set as well). */
+#define MAP_FLAG_EARLY 0x20u
 
 /* Result of map_propagate / map_detect, written to device memory (32 bytes). */
 typedef struct map_result {

@@ -48,6 +48,7 @@ MAP_FLAG_NO_TRACE_DIGEST = 0x2
 MAP_FLAG_STREAM = 0x4
 MAP_FLAG_SYNC_SWEEPS = 0x8
 MAP_FLAG_PUSH = 0x10
+MAP_FLAG_EARLY = 0x20
 
 EXPORTS = ("map_workspace_bytes", "map_build_csr", "map_propagate", "map_detect", "map_batch_workspace_bytes",
            "map_detect_batch", "map_job_scratch_bytes", "map_engine_create", "map_engine_workgroups",

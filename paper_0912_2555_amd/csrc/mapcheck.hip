@@ -49,7 +49,8 @@ constexpr int kSortSlots = 1024;                        // resident mode: bitoni
 constexpr int kSortPerLane = kSortSlots / kWave;
 static_assert(kSortSlots >= kWave * kGatherBatch, "sort must cover a gather batch");
 constexpr uint32_t kAllFlags =
-    MAP_FLAG_DENSE_ONLY | MAP_FLAG_NO_TRACE_DIGEST | MAP_FLAG_STREAM | MAP_FLAG_SYNC_SWEEPS | MAP_FLAG_PUSH;
+    MAP_FLAG_DENSE_ONLY | MAP_FLAG_NO_TRACE_DIGEST | MAP_FLAG_STREAM | MAP_FLAG_SYNC_SWEEPS | MAP_FLAG_PUSH |
+    MAP_FLAG_EARLY;
 constexpr uint32_t kAccBit = 0x80000000u;
 
 // Global-memory views of device pointers, for out-of-line functions where the
@@ -106,7 +107,8 @@ struct alignas(256) CtrlT {
   unsigned long long scanned;       // lasso: edges examined
   uint32_t kept;                    // trim: vertices kept
   uint32_t acc_kept;                // trim: accepting vertices kept
-  uint32_t pad3[24];
+  uint32_t early;                   // MAP_FLAG_EARLY: largest id seen equal to its own value (0: none)
+  uint32_t pad3[23];
   unsigned long long quiet[Q];
 };
 using Ctrl = CtrlT<kMaxBlocks>;
@@ -272,6 +274,7 @@ struct LoopArgs {
   uint32_t val_mask;     // bits of a packed word holding the map value
   uint32_t par_bit;      // bit holding the iteration parity (0: untagged, n >= 2^30)
   int32_t push;          // 1: frontier sweeps over the transposed CSR (barrier per round)
+  int32_t early;         // 1: stop once a value equals its own row's id (MAP_FLAG_EARLY)
   const int32_t* rrow_ptr;  // push: transposed CSR (row w = predecessors of w)
   const int32_t* rcol;
   int32_t* front[2];     // push: frontier lists, int32[n] each
@@ -324,6 +327,14 @@ struct WaveRows {
 // mode g_lds.res.pv holds the block's own packed values, the only copy a wave
 // reads its rows from.
 __shared__ BlockLds g_lds;
+// MAP_FLAG_EARLY: the largest id of a row of this block whose value became
+// its own id during the current sweep (0: none).
+__shared__ uint32_t g_early;
+
+// Records row v (0-based) if its new value x is its own id.
+__device__ __forceinline__ void early_check(const LoopArgs& a, uint32_t x, int64_t v) {
+  if (a.early && (x & a.val_mask) == (uint32_t)v + 1u) atomicMax(&g_early, (uint32_t)v + 1u);
+}
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -410,9 +421,11 @@ __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int64_t r0
         nacc += isacc;
         pv[v] = (isacc << 31) | cur | best[j];
         changed |= (best[j] | isacc) != 0;
+        early_check(a, best[j], v);
       } else if (best[j] > (old[j] & vmask)) {
         pv[v] = (old[j] & ~vmask) | best[j];
         changed = 1;
+        early_check(a, best[j], v);
       }
     }
   }
@@ -489,6 +502,7 @@ __device__ uint32_t local_pass(const LoopArgs& a, const WaveRows& W, int lane, u
         pv[(int64_t)base + li] = x;
         R.pv[li] = x;
         changed = 1;
+        early_check(a, b, (int64_t)base + li);
       }
     }
   }
@@ -531,6 +545,7 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, const 
         pv[v] = x;
         R.pv[li] = x;
         changed |= (b | isacc) != 0;
+        early_check(a, b, v);
       } else {
         const uint32_t old = R.pv[li];
         if (b > (old & vmask)) {
@@ -538,6 +553,7 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, const 
           pv[v] = x;
           R.pv[li] = x;
           changed = 1;
+          early_check(a, b, v);
         }
       }
     }
@@ -698,6 +714,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
 
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = threadIdx.x / kWave;
+  if (threadIdx.x == 0) g_early = 0;  // ordered before its first use by the set-up's barriers
 
   // Row ranges of this block and wave.
   const int64_t rows_per_block = ((int64_t)a.n + nb - 1) / nb;
@@ -894,6 +911,11 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     // After a sweep: the barrier (sync) or the change / quiet report (async).
     // Returns false when the launch must stop.
     auto report = [&](uint32_t any, uint32_t d0) -> bool {
+      // A row that reached its own id in this sweep (block_any's barrier has
+      // ordered every wave's record before this read); published before the
+      // barrier or the release below.
+      if (a.early && threadIdx.x == 0 && g_early)
+        __hip_atomic_fetch_max(&c->early, g_early, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (sync) {
         if (s == 1 && !a.propagate) block_add_count(nacc, g.gen % kSets);
         if (!grid_sync(g, any, &tot)) return false;
@@ -1025,6 +1047,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
       uint32_t d0 = 0;
       if (sync) {
         if (tot == 0) break;
+        if (a.early && ld_agent(&c->early)) break;  // read after the barrier: the same in every block
         if (s > (int64_t)a.n + 1) { status = MAP_ENOTCONVERGED; break; }
       } else {
         if (wib == 0) {
@@ -1032,6 +1055,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
           const uint64_t t0 = wall_clock64();
           for (;;) {
             if (ld_agent(&c->done) == tag) { cmd = 1; break; }
+            if (a.early && ld_agent(&c->early)) { cmd = 1; break; }
             const uint32_t d = ld_agent(&c->dirty);
             if (d != d_seen) { cmd = 0; d0 = d; break; }
             if (b == 0) {
@@ -1125,6 +1149,9 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
       nz2 = wave_sum_u32(nz2);
       cnt2 = wave_sum_u32(cnt2);
       if (!sync) cnt_k = cnt2;
+      // MAP_FLAG_EARLY: a published early hit (every block's publication
+      // precedes its arrival at the barrier above) is a cycle vertex too.
+      if (a.early) w2 = max(w2, (int32_t)ld_agent(&c->early));
       const bool leader = b == 0 && threadIdx.x == 0;
       if (k >= 2 && cnt_k == 0) {
         // No accepting vertex was left after iteration k-1: iteration k did not happen.
@@ -1707,6 +1734,7 @@ __device__ LoopArgs gang_args(int32_t n, const int32_t* row_ptr, const int32_t* 
   a.val_mask = n < (1 << 30) ? 0x3fffffffu : kValMask;
   a.par_bit = n < (1 << 30) ? 0x40000000u : 0u;
   a.push = 0;
+  a.early = (flags & MAP_FLAG_EARLY) ? 1 : 0;
   a.rrow_ptr = nullptr;
   a.rcol = nullptr;
   a.front[0] = a.front[1] = nullptr;
@@ -2605,6 +2633,10 @@ int map_detect(int32_t n, const int32_t* row_ptr, const int32_t* col, const int3
   a.sync_sweeps = (flags & MAP_FLAG_SYNC_SWEEPS) ? 1 : 0;
   rc = push_setup(a, rrow_ptr, rcol, flags, ws);
   if (rc) return rc;
+  if (flags & MAP_FLAG_EARLY) {
+    if (a.push) return MAP_EINVAL;
+    a.early = 1;
+  }
   return launch_loop(a, reinterpret_cast<hipStream_t>(stream));
 }
 

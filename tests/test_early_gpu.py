@@ -1,0 +1,118 @@
+"""Early in-propagation detection (MAP_FLAG_EARLY), through the C ABI.
+
+With the flag the loop stops as soon as some vertex's value equals its own id
+during a propagation.  The verdict must equal the full run's (and the
+oracle's); the witness is schedule-dependent, so it is checked for what makes
+it a witness -- accepting in A_1 and on a cycle (Tarjan's components, or a
+self-loop) -- and K may only shrink.  On graphs without an accepting cycle the
+flag can never fire, and every result field equals the plain run's.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    import paper_0912_2555_amd as mc
+    return mc
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def on_cycle(g):
+    _, comp = oracle.tarjan(g, with_components=True)
+    sizes = np.bincount(comp)
+    cyc = sizes[comp] >= 2
+    cyc[g.src[g.src == g.dst] - 1] = True
+    return cyc
+
+
+def check(mc, g, flags=0):
+    say("early", g.name, "n", g.n, "m", len(g.src), "flags", flags)
+    ref = oracle.map_detect(g)
+    csr = mc.build_csr(g.n, g.src, g.dst)
+    early = mc.detect(csr, g.acc, flags=flags | mc.MAP_FLAG_EARLY).result
+    plain = mc.detect(csr, g.acc, flags=flags).result
+    assert early.status == 0 and plain.status == 0
+    assert plain.verdict == ref.verdict
+    assert early.found == ref.found
+    if ref.found:
+        w = early.witness
+        assert 1 <= w <= g.n and g.acc[w - 1] == 1, w
+        assert on_cycle(g)[w - 1], w
+        assert 1 <= early.iterations <= ref.iterations
+    else:
+        assert (early.witness, early.iterations, early.accepting_left) == (0, ref.iterations, ref.accepting_left)
+    say("  K early", early.iterations, "K full", ref.iterations, "witness", early.witness, "vs", ref.witness)
+    return early
+
+
+CASES = [lambda: synth.from_edges(5, [(1, 2), (2, 3), (3, 1), (3, 4), (4, 5)], [2, 4, 5], "hand"),
+         lambda: synth.from_edges(2, [(1, 1), (1, 2), (2, 2)], [1, 2], "loops"),
+         lambda: synth.config1(),
+         lambda: synth.config1(dag=True),
+         lambda: synth.config2(seed=3, n=1 << 15, planted=True),
+         lambda: synth.config2(seed=5, n=1 << 16, planted=True),
+         lambda: synth.config2(seed=7, n=1 << 16),
+         lambda: synth.config3(n=1 << 16)]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("flags", [0, 0x8, 0x4])  # default, MAP_FLAG_SYNC_SWEEPS, MAP_FLAG_STREAM
+def test_early_verdicts(mc, case, flags):
+    check(mc, CASES[case](), flags)
+
+
+def test_random_graphs(mc):
+    for seed in range(12):
+        rng = np.random.default_rng(500 + seed)
+        n = int(rng.integers(50, 3000))
+        g = synth.random_graph(seed, n, int(n * rng.uniform(0.8, 1.6)), p_acc=float(rng.uniform(0.02, 0.3)))
+        check(mc, g)
+
+
+def test_full_size_config2(mc):
+    e = check(mc, synth.config2(planted=True))
+    assert e.iterations <= 1050   # the planted cycle only becomes its own maximum once larger ids are stripped
+    check(mc, synth.config2())
+
+
+def test_push_with_early_rejected(mc):
+    import torch
+    g = synth.config2(seed=3, n=1 << 12, planted=True)
+    csr = mc.build_csr(g.n, g.src, g.dst)
+    acc = torch.from_numpy(g.acc).cuda()
+    ws = mc.workspace(g.n, g.m)
+    res = mc.new_result()
+    rc = mc.map_detect(g.n, csr.row_ptr, csr.col, csr.rrow_ptr, csr.rcol, acc, res, None, None, 0,
+                       mc.MAP_FLAG_PUSH | mc.MAP_FLAG_EARLY, ws)
+    assert rc == mc.MAP_EINVAL
+    rc = mc.map_detect(g.n, csr.row_ptr, csr.col, csr.rrow_ptr, csr.rcol, acc, res, None, None, 0,
+                       mc.MAP_FLAG_PUSH | mc.MAP_FLAG_EARLY | mc.MAP_FLAG_DENSE_ONLY, ws)
+    assert rc == mc.MAP_OK
+
+
+def test_batch_with_early(mc):
+    graphs = [synth.config4(i) for i in range(24)]
+    csrs = [mc.build_csr(g.n, g.src, g.dst, transposed=False) for g in graphs]
+    b = mc.Batch(csrs, [g.acc for g in graphs], gang=[1 + (i % 3) for i in range(24)], flags=mc.MAP_FLAG_EARLY)
+    b.launch()
+    for g, r in zip(graphs, b.read()):
+        ref = oracle.map_detect(g)
+        assert r.status == 0 and r.found == ref.found, g.name
+        if ref.found:
+            assert g.acc[r.witness - 1] == 1 and on_cycle(g)[r.witness - 1] and r.iterations <= ref.iterations
+        else:
+            assert (r.iterations, r.accepting_left) == (ref.iterations, ref.accepting_left)
