@@ -327,14 +327,9 @@ struct WaveRows {
 // mode g_lds.res.pv holds the block's own packed values, the only copy a wave
 // reads its rows from.
 __shared__ BlockLds g_lds;
-// MAP_FLAG_EARLY: the largest id of a row of this block whose value became
-// its own id during the current sweep (0: none).
+// MAP_FLAG_EARLY: the largest id of a row of this block whose value equals
+// its own id (0: none), found by a scan of the block's rows after each sweep.
 __shared__ uint32_t g_early;
-
-// Records row v (0-based) if its new value x is its own id.
-__device__ __forceinline__ void early_check(const LoopArgs& a, uint32_t x, int64_t v) {
-  if (a.early && (x & a.val_mask) == (uint32_t)v + 1u) atomicMax(&g_early, (uint32_t)v + 1u);
-}
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -421,11 +416,9 @@ __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int64_t r0
         nacc += isacc;
         pv[v] = (isacc << 31) | cur | best[j];
         changed |= (best[j] | isacc) != 0;
-        early_check(a, best[j], v);
       } else if (best[j] > (old[j] & vmask)) {
         pv[v] = (old[j] & ~vmask) | best[j];
         changed = 1;
-        early_check(a, best[j], v);
       }
     }
   }
@@ -502,7 +495,6 @@ __device__ uint32_t local_pass(const LoopArgs& a, const WaveRows& W, int lane, u
         pv[(int64_t)base + li] = x;
         R.pv[li] = x;
         changed = 1;
-        early_check(a, b, (int64_t)base + li);
       }
     }
   }
@@ -545,7 +537,6 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, const 
         pv[v] = x;
         R.pv[li] = x;
         changed |= (b | isacc) != 0;
-        early_check(a, b, v);
       } else {
         const uint32_t old = R.pv[li];
         if (b > (old & vmask)) {
@@ -553,7 +544,6 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, const 
           pv[v] = x;
           R.pv[li] = x;
           changed = 1;
-          early_check(a, b, v);
         }
       }
     }
@@ -705,7 +695,7 @@ __device__ __forceinline__ uint32_t frontier_append(int32_t* F, uint32_t* cnt, b
 // kAsync selects the fixpoint control at compile time: asynchronous sweeps with
 // quiescence detection, or a grid barrier after every sweep (required for a
 // single block, for untagged values, and with MAP_FLAG_SYNC_SWEEPS).
-template <typename C, bool kAsync>
+template <typename C, bool kAsync, bool kEarly>
 __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, const int logical) {
   BlockLds& S = g_lds;
   __shared__ uint32_t s_red[kWavesPerBlock];
@@ -714,7 +704,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
 
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = threadIdx.x / kWave;
-  if (threadIdx.x == 0) g_early = 0;  // ordered before its first use by the set-up's barriers
+  if (kEarly && threadIdx.x == 0) g_early = 0;  // ordered before its first use by the set-up's barriers
 
   // Row ranges of this block and wave.
   const int64_t rows_per_block = ((int64_t)a.n + nb - 1) / nb;
@@ -914,7 +904,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
       // A row that reached its own id in this sweep (block_any's barrier has
       // ordered every wave's record before this read); published before the
       // barrier or the release below.
-      if (a.early && threadIdx.x == 0 && g_early)
+      if (kEarly && threadIdx.x == 0 && g_early)
         __hip_atomic_fetch_max(&c->early, g_early, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (sync) {
         if (s == 1 && !a.propagate) block_add_count(nacc, g.gen % kSets);
@@ -941,6 +931,16 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
         return false;
       }
       return true;
+    };
+    // MAP_FLAG_EARLY: after a sweep, the block's rows whose value is their
+    // own id (kept out of the sweep code, whose register allocation it would
+    // otherwise share); block_any's barrier orders the records before report
+    // reads them.
+    auto early_scan = [&]() {
+      if (!kEarly) return;
+      for_own_rows(a, W, lane, [&](int64_t v, uint32_t x) {
+        if ((x & a.val_mask) == (uint32_t)v + 1u) atomicMax(&g_early, (uint32_t)v + 1u);
+      });
     };
     // Sum over the block of a per-wave count (every thread gets it).
     auto block_sum_waves = [&](uint32_t x) {
@@ -1041,13 +1041,14 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
       }
       const uint32_t c1 = sweep_rows<true>(a, acc, W, wib, lane, cur, &nacc, &local_fix);
       s = 1;
+      early_scan();
       if (!report(block_any(c1), d0)) goto aborted;
     }
     for (;;) {
       uint32_t d0 = 0;
       if (sync) {
         if (tot == 0) break;
-        if (a.early && ld_agent(&c->early)) break;  // read after the barrier: the same in every block
+        if (kEarly && ld_agent(&c->early)) break;  // read after the barrier: the same in every block
         if (s > (int64_t)a.n + 1) { status = MAP_ENOTCONVERGED; break; }
       } else {
         if (wib == 0) {
@@ -1055,7 +1056,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
           const uint64_t t0 = wall_clock64();
           for (;;) {
             if (ld_agent(&c->done) == tag) { cmd = 1; break; }
-            if (a.early && ld_agent(&c->early)) { cmd = 1; break; }
+            if (kEarly && ld_agent(&c->early)) { cmd = 1; break; }
             const uint32_t d = ld_agent(&c->dirty);
             if (d != d_seen) { cmd = 0; d0 = d; break; }
             if (b == 0) {
@@ -1088,6 +1089,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
       }
       const uint32_t c2 = sweep_rows<false>(a, acc, W, wib, lane, cur, nullptr, &local_fix);
       s++;
+      early_scan();
       if (!report(block_any(c2), d0)) goto aborted;
     }
     }
@@ -1151,7 +1153,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
       if (!sync) cnt_k = cnt2;
       // MAP_FLAG_EARLY: a published early hit (every block's publication
       // precedes its arrival at the barrier above) is a cycle vertex too.
-      if (a.early) w2 = max(w2, (int32_t)ld_agent(&c->early));
+      if (kEarly) w2 = max(w2, (int32_t)ld_agent(&c->early));
       const bool leader = b == 0 && threadIdx.x == 0;
       if (k >= 2 && cnt_k == 0) {
         // No accepting vertex was left after iteration k-1: iteration k did not happen.
@@ -1223,14 +1225,16 @@ aborted:
   __syncthreads();
 }
 
-template <bool kAsync>
+// kEarly: MAP_FLAG_EARLY (a separate instantiation, so that the plain loop
+// carries none of its code).
+template <bool kAsync, bool kEarly>
 __global__ void __launch_bounds__(kBlock) map_loop_kernel(LoopArgs a) {
   const int nb = gridDim.x;
   const int b = blockIdx.x;
   // XCD-aware numbering: consecutive hardware block ids land on different
   // XCDs; give each XCD a contiguous range of logical blocks (and rows).
   const int logical = (nb % kMaxGroups == 0) ? (b % kMaxGroups) * (nb / kMaxGroups) + b / kMaxGroups : b;
-  map_body<Ctrl, kAsync>(a, a.ctrl, nb, b, logical);
+  map_body<Ctrl, kAsync, kEarly>(a, a.ctrl, nb, b, logical);
 }
 
 // ------------------------------------------------------------------ batch --
@@ -1251,10 +1255,27 @@ struct BatchArgs {
 // One graph of a batch, out of line so that its register allocation is not
 // shared with the work-queue loop around it.
 __device__ __noinline__ void map_body_gang_async(const LoopArgs& a, GangCtrl* c, int nb, int rank) {
-  map_body<GangCtrl, true>(a, c, nb, rank, rank);
+  map_body<GangCtrl, true, false>(a, c, nb, rank, rank);
 }
 __device__ __noinline__ void map_body_gang_sync(const LoopArgs& a, GangCtrl* c, int nb, int rank) {
-  map_body<GangCtrl, false>(a, c, nb, rank, rank);
+  map_body<GangCtrl, false, false>(a, c, nb, rank, rank);
+}
+__device__ __noinline__ void map_body_gang_async_early(const LoopArgs& a, GangCtrl* c, int nb, int rank) {
+  map_body<GangCtrl, true, true>(a, c, nb, rank, rank);
+}
+__device__ __noinline__ void map_body_gang_sync_early(const LoopArgs& a, GangCtrl* c, int nb, int rank) {
+  map_body<GangCtrl, false, true>(a, c, nb, rank, rank);
+}
+// One graph solved by a gang, in the fixpoint control and mode its arguments ask for.
+__device__ __forceinline__ void map_body_gang(const LoopArgs& a, GangCtrl* c, int nb, int rank) {
+  const bool async = nb > 1 && !a.sync_sweeps && a.par_bit;
+  if (a.early) {
+    if (async) map_body_gang_async_early(a, c, nb, rank);
+    else map_body_gang_sync_early(a, c, nb, rank);
+  } else {
+    if (async) map_body_gang_async(a, c, nb, rank);
+    else map_body_gang_sync(a, c, nb, rank);
+  }
 }
 
 // --------------------------------------------------------- counterexample --
@@ -1780,8 +1801,7 @@ __global__ void __launch_bounds__(kBlock) map_batch_kernel(BatchArgs ba) {
     }
     char* base = ba.scratch + ba.scratch_off[gi];
     const LoopArgs a = gang_args(d.n, d.row_ptr, d.col, d.accepting0, base, ba.results + gi, ba.flags);
-    if (nb > 1 && !a.sync_sweeps && a.par_bit) map_body_gang_async(a, ba.gctrl + gi, nb, rank);
-    else map_body_gang_sync(a, ba.gctrl + gi, nb, rank);
+    map_body_gang(a, ba.gctrl + gi, nb, rank);
   }
 }
 
@@ -2061,8 +2081,7 @@ __device__ __noinline__ void engine_job(const EngineArgs& ea, int slot, int rank
   }
   if (ok && bad == 0) {
     const LoopArgs a = gang_args(j.n, j.row_ptr, j.col, j.accepting0, sc, res, ea.flags);
-    if (nb > 1 && !a.sync_sweeps && a.par_bit) map_body_gang_async(a, mcx, nb, rank);
-    else map_body_gang_sync(a, mcx, nb, rank);
+    map_body_gang(a, mcx, nb, rank);
   }
   // Leave the job: release this block's writes, then report (ranks > 0) or
   // wait for the others and publish the result (rank 0).
@@ -2384,7 +2403,7 @@ int device_info(DeviceInfo* out) {
     int cus = 0, coop = 0, nb = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return MAP_EDEVICE;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) return MAP_EDEVICE;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(map_loop_kernel<true>), kBlock,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(map_loop_kernel<true, false>), kBlock,
                                                      0) != hipSuccess)
       return MAP_EDEVICE;
     if (cus <= 0 || nb <= 0) return MAP_EDEVICE;
@@ -2412,8 +2431,11 @@ int launch_loop(LoopArgs& a, hipStream_t stream) {
   if (hipGetLastError() != hipSuccess) return MAP_EDEVICE;
   void* args[] = {&a};
   const bool async = grid > 1 && !a.sync_sweeps && a.par_bit != 0;
-  const void* kernel = async ? reinterpret_cast<const void*>(map_loop_kernel<true>)
-                             : reinterpret_cast<const void*>(map_loop_kernel<false>);
+  const void* kernel =
+      a.early ? (async ? reinterpret_cast<const void*>(map_loop_kernel<true, true>)
+                       : reinterpret_cast<const void*>(map_loop_kernel<false, true>))
+              : (async ? reinterpret_cast<const void*>(map_loop_kernel<true, false>)
+                       : reinterpret_cast<const void*>(map_loop_kernel<false, false>));
   if (hipLaunchCooperativeKernel(kernel, dim3((unsigned)grid), dim3(kBlock), args, 0, stream) != hipSuccess)
     return MAP_EDEVICE;
   return MAP_OK;
