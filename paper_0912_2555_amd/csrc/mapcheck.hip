@@ -26,7 +26,9 @@
 #include <atomic>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "mapcheck.h"
@@ -1280,6 +1282,20 @@ __device__ __forceinline__ void map_body_gang(const LoopArgs& a, GangCtrl* c, in
 
 // --------------------------------------------------------- counterexample --
 
+// Barrier state of a launch whose blocks all cooperate on one control block,
+// in hardware block order.
+__device__ __forceinline__ Grid<Ctrl> whole_grid(Ctrl* c) {
+  Grid<Ctrl> g;
+  g.c = c;
+  g.gen = 0;
+  g.nblocks = gridDim.x;
+  g.ngroups = min((int)gridDim.x, kMaxGroups);
+  g.group = blockIdx.x % g.ngroups;
+  g.group_size = gridDim.x / g.ngroups + ((blockIdx.x % g.ngroups) < (gridDim.x % g.ngroups) ? 1 : 0);
+  g.rank = blockIdx.x;
+  return g;
+}
+
 // Arguments of the lasso search: a shortest path from `init` to the witness
 // and a shortest cycle through it, by breadth-first search over successors.
 struct LassoArgs {
@@ -1493,14 +1509,7 @@ __device__ bool lasso_walk(const LassoArgs& a, int32_t x, int32_t hi, int32_t lo
 }
 
 __global__ void __launch_bounds__(kBlock) map_lasso_kernel(LassoArgs a) {
-  Grid<Ctrl> g;
-  g.c = a.ctrl;
-  g.gen = 0;
-  g.nblocks = gridDim.x;
-  g.ngroups = min((int)gridDim.x, kMaxGroups);
-  g.group = blockIdx.x % g.ngroups;
-  g.group_size = gridDim.x / g.ngroups + ((blockIdx.x % g.ngroups) < (gridDim.x % g.ngroups) ? 1 : 0);
-  g.rank = blockIdx.x;
+  Grid<Ctrl> g = whole_grid(a.ctrl);
   const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
   unsigned long long scanned = 0;
   int32_t levels = 0, S = 0, L = -1, last = 0;
@@ -1594,14 +1603,7 @@ struct TrimArgs {
 // always keeps an in-edge and an out-edge from the cycle, so it is never
 // removed.
 __global__ void __launch_bounds__(kBlock) map_trim_kernel(TrimArgs a) {
-  Grid<Ctrl> g;
-  g.c = a.ctrl;
-  g.gen = 0;
-  g.nblocks = gridDim.x;
-  g.ngroups = min((int)gridDim.x, kMaxGroups);
-  g.group = blockIdx.x % g.ngroups;
-  g.group_size = gridDim.x / g.ngroups + ((blockIdx.x % g.ngroups) < (gridDim.x % g.ngroups) ? 1 : 0);
-  g.rank = blockIdx.x;
+  Grid<Ctrl> g = whole_grid(a.ctrl);
   Ctrl* c = a.ctrl;
   const int lane = threadIdx.x & (kWave - 1), wib = threadIdx.x / kWave;
   const int64_t gw = (int64_t)g.rank * kWavesPerBlock + wib, nw = (int64_t)g.nblocks * kWavesPerBlock;
@@ -2532,6 +2534,40 @@ int engine_device_info(int* cus, int* per_cu, int* wall_khz) {
   return MAP_OK;
 }
 
+// Grid of a cooperative frontier launch (counterexample search, pruning):
+// about one workgroup per 4096 vertices and at most one per CU — a round's
+// frontier is usually far smaller than the graph, and fewer workgroups make the
+// per-round barrier cheaper.  Limits are cached per device and kernel.
+int frontier_grid(const void* kernel, int32_t n, int64_t* grid_out) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, std::pair<int, int>> cache;  // -> (CUs, blocks per CU)
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MAP_EDEVICE;
+  int cus = 0, per = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({dev, kernel});
+    if (it == cache.end()) {
+      int co = 0;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return MAP_EDEVICE;
+      if (hipDeviceGetAttribute(&co, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) return MAP_EDEVICE;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess) return MAP_EDEVICE;
+      if (cus <= 0 || per <= 0 || !co) return MAP_EDEVICE;
+      it = cache.emplace(std::make_pair(dev, kernel), std::make_pair(cus, per)).first;
+    }
+    cus = it->second.first;
+    per = it->second.second;
+  }
+  int64_t grid = ((int64_t)n + 4095) / 4096;
+  if (grid > (int64_t)cus * per) grid = (int64_t)cus * per;
+  if (grid > cus) grid = cus;
+  if (grid > kMaxBlocks) grid = kMaxBlocks;
+  if (grid >= kMaxGroups) grid -= grid % kMaxGroups;
+  if (grid < 1) grid = 1;
+  *grid_out = grid;
+  return MAP_OK;
+}
+
 constexpr int32_t kEngineRing = 1 << 17;  // ticket ring entries (1 MiB of host memory)
 
 }  // namespace
@@ -2669,39 +2705,9 @@ int map_lasso(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t wit
   if (witness < 1 || witness > n || init < 0 || init > n) return MAP_EINVAL;
   const Layout L = layout(n);
   if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return MAP_ENOSPC;
-  static std::mutex mu;
-  static int cache_cus[64], cache_per[64], cache_coop[64];
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return MAP_EDEVICE;
-  int cus, per, coop;
-  {
-    std::lock_guard<std::mutex> lock(mu);
-    if (cache_cus[dev] == 0) {
-      int c = 0, nb = 0, co = 0;
-      if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return MAP_EDEVICE;
-      if (hipDeviceGetAttribute(&co, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) return MAP_EDEVICE;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(map_lasso_kernel), kBlock,
-                                                       0) != hipSuccess)
-        return MAP_EDEVICE;
-      if (c <= 0 || nb <= 0) return MAP_EDEVICE;
-      cache_cus[dev] = c;
-      cache_per[dev] = nb;
-      cache_coop[dev] = co;
-    }
-    cus = cache_cus[dev];
-    per = cache_per[dev];
-    coop = cache_coop[dev];
-  }
-  if (!coop) return MAP_EDEVICE;
-  // About one workgroup per 4096 vertices, at most one per CU: a round's
-  // frontier is usually far smaller than the graph, and fewer workgroups make
-  // the per-round barrier cheaper.
-  int64_t grid = ((int64_t)n + 4095) / 4096;
-  if (grid > (int64_t)cus * per) grid = (int64_t)cus * per;
-  if (grid > cus) grid = cus;
-  if (grid > kMaxBlocks) grid = kMaxBlocks;
-  if (grid >= kMaxGroups) grid -= grid % kMaxGroups;
-  if (grid < 1) grid = 1;
+  int64_t grid = 0;
+  int rc = frontier_grid(reinterpret_cast<const void*>(map_lasso_kernel), n, &grid);
+  if (rc) return rc;
   char* w = static_cast<char*>(ws);
   LassoArgs a;
   a.n = n;
@@ -2735,39 +2741,9 @@ int map_trim(int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_
   if ((accepting == nullptr) != (accepting_out == nullptr)) return MAP_EINVAL;
   const Layout L = layout(n);
   if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return MAP_ENOSPC;
-  static std::mutex mu;
-  static int cache_cus[64], cache_per[64], cache_coop[64];
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return MAP_EDEVICE;
-  int cus, per, coop;
-  {
-    std::lock_guard<std::mutex> lock(mu);
-    if (cache_cus[dev] == 0) {
-      int c = 0, nb = 0, co = 0;
-      if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return MAP_EDEVICE;
-      if (hipDeviceGetAttribute(&co, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) return MAP_EDEVICE;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(map_trim_kernel), kBlock,
-                                                       0) != hipSuccess)
-        return MAP_EDEVICE;
-      if (c <= 0 || nb <= 0) return MAP_EDEVICE;
-      cache_cus[dev] = c;
-      cache_per[dev] = nb;
-      cache_coop[dev] = co;
-    }
-    cus = cache_cus[dev];
-    per = cache_per[dev];
-    coop = cache_coop[dev];
-  }
-  if (!coop) return MAP_EDEVICE;
-  // About one workgroup per 4096 vertices, at most one per CU (the rounds
-  // usually hold far fewer vertices than the graph; fewer workgroups make the
-  // per-round barrier cheaper).
-  int64_t grid = ((int64_t)n + 4095) / 4096;
-  if (grid > (int64_t)cus * per) grid = (int64_t)cus * per;
-  if (grid > cus) grid = cus;
-  if (grid > kMaxBlocks) grid = kMaxBlocks;
-  if (grid >= kMaxGroups) grid -= grid % kMaxGroups;
-  if (grid < 1) grid = 1;
+  int64_t grid = 0;
+  int rc = frontier_grid(reinterpret_cast<const void*>(map_trim_kernel), n, &grid);
+  if (rc) return rc;
   char* w = static_cast<char*>(ws);
   TrimArgs a;
   a.n = n;

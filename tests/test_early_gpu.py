@@ -61,6 +61,8 @@ def check(mc, g, flags=0):
 
 CASES = [lambda: synth.from_edges(5, [(1, 2), (2, 3), (3, 1), (3, 4), (4, 5)], [2, 4, 5], "hand"),
          lambda: synth.from_edges(2, [(1, 1), (1, 2), (2, 2)], [1, 2], "loops"),
+         lambda: synth.from_edges(1, [(1, 1)], [1], "one-loop"),
+         lambda: synth.from_edges(3, [(1, 2), (2, 3), (3, 1)], [], "no-accepting"),
          lambda: synth.config1(),
          lambda: synth.config1(dag=True),
          lambda: synth.config2(seed=3, n=1 << 15, planted=True),
