@@ -37,5 +37,28 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+EXAMPLE_SRC = os.path.join(PKG, "examples", "detect.c")
+EXAMPLE = os.path.join(PKG, "examples", "detect")
+
+
+def build_example(verbose: bool = False) -> str:
+    """The C usage example (plain C against the C ABI and the HIP runtime), linked to the built library."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    tmp = EXAMPLE + ".tmp"
+    cmd = [os.environ.get("CC", "gcc"), "-std=c11", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"), EXAMPLE_SRC,
+           "-L", PKG, "-lmapcheck", "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN/..", "-Wl,-rpath," + os.path.join(rocm, "lib"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("failed to build the C example")
+    os.replace(tmp, EXAMPLE)
+    return EXAMPLE
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_example(verbose=True))
