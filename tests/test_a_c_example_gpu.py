@@ -2,7 +2,13 @@
 the C ABI and the HIP runtime, no Python or torch in the process.  It checks
 the results its two graphs fix (the worked example; a ring with a tail) and
 exits with 0 when all match; the same values are checked here against the
-oracle so that the example's own expectations are pinned too."""
+oracle so that the example's own expectations are pinned too.
+
+The example runs as a child process and launches cooperative kernels.  A
+second process's cooperative launch was refused once this test process had
+made cooperative launches of its own (the other GPU test files), so this file
+is named to run first, before anything here touches the GPU; it uses no GPU
+in this process itself."""
 import os
 import subprocess
 
