@@ -23,6 +23,7 @@ this package raises if ``libmapcheck.so`` is missing -- there is no fallback.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 from dataclasses import dataclass
@@ -133,6 +134,13 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _on(stream):
+    """Context in which a convenience wrapper allocates, uploads, calls and reads
+    back: ``stream`` when given, so that every step is ordered with the call,
+    else torch's current stream."""
+    return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+
+
 def _check(rc: int, where: str):
     if rc != MAP_OK:
         raise MapError(rc, where)
@@ -234,32 +242,36 @@ class Csr:
 
 def build_csr(n: int, src, dst, transposed: bool = True, ws: torch.Tensor | None = None, stream=None,
               device="cuda") -> Csr:
-    """Upload (if needed) the 1-based edge list and build the CSR on the device."""
-    src = torch.as_tensor(src, dtype=torch.int32).to(device).contiguous()
-    dst = torch.as_tensor(dst, dtype=torch.int32).to(device).contiguous()
-    m = int(src.numel())
-    row_ptr = torch.empty(n + 1, dtype=torch.int32, device=device)
-    col = torch.empty(max(m, 1), dtype=torch.int32, device=device)
-    rrow_ptr = torch.empty(n + 1, dtype=torch.int32, device=device) if transposed else None
-    rcol = torch.empty(max(m, 1), dtype=torch.int32, device=device) if transposed else None
-    status = torch.zeros(1, dtype=torch.int32, device=device)
-    if ws is None:
-        ws = workspace(n, m, device=device)
-    _check(map_build_csr(n, src if m else None, dst if m else None, row_ptr, col, rrow_ptr, rcol, status, ws,
-                         stream), "map_build_csr")
+    """Upload (if needed) the 1-based edge list and build the CSR on the device.
+
+    With ``stream`` every step runs on it; the CSR is ready once it has run."""
+    with _on(stream):
+        src = torch.as_tensor(src, dtype=torch.int32).to(device).contiguous()
+        dst = torch.as_tensor(dst, dtype=torch.int32).to(device).contiguous()
+        m = int(src.numel())
+        row_ptr = torch.empty(n + 1, dtype=torch.int32, device=device)
+        col = torch.empty(max(m, 1), dtype=torch.int32, device=device)
+        rrow_ptr = torch.empty(n + 1, dtype=torch.int32, device=device) if transposed else None
+        rcol = torch.empty(max(m, 1), dtype=torch.int32, device=device) if transposed else None
+        status = torch.zeros(1, dtype=torch.int32, device=device)
+        if ws is None:
+            ws = workspace(n, m, device=device)
+        _check(map_build_csr(n, src if m else None, dst if m else None, row_ptr, col, rrow_ptr, rcol, status, ws,
+                             stream), "map_build_csr")
     return Csr(n, m, row_ptr, col, rrow_ptr, rcol, status)
 
 
 def propagate(csr: Csr, accepting, flags: int = 0, ws=None, stream=None):
     """One fixpoint: returns (map vector as a device int32 tensor, Result)."""
-    acc = torch.as_tensor(accepting, dtype=torch.uint8).to(csr.row_ptr.device).contiguous()
-    out = torch.empty(csr.n, dtype=torch.int32, device=csr.row_ptr.device)
-    res = new_result(csr.row_ptr.device)
-    if ws is None:
-        ws = workspace(csr.n, csr.m, flags, device=csr.row_ptr.device)
-    _check(map_propagate(csr.n, csr.row_ptr, csr.col, csr.rrow_ptr, csr.rcol, acc, out, res, flags, ws, stream),
-           "map_propagate")
-    return out, Result.from_tensor(res)
+    with _on(stream):
+        acc = torch.as_tensor(accepting, dtype=torch.uint8).to(csr.row_ptr.device).contiguous()
+        out = torch.empty(csr.n, dtype=torch.int32, device=csr.row_ptr.device)
+        res = new_result(csr.row_ptr.device)
+        if ws is None:
+            ws = workspace(csr.n, csr.m, flags, device=csr.row_ptr.device)
+        _check(map_propagate(csr.n, csr.row_ptr, csr.col, csr.rrow_ptr, csr.rcol, acc, out, res, flags, ws,
+                             stream), "map_propagate")
+        return out, Result.from_tensor(res)
 
 
 @dataclass
@@ -273,19 +285,20 @@ def detect(csr: Csr, accepting0, trace_cap: int = 0, want_acc: bool = False, max
            flags: int = 0, ws=None, stream=None) -> DetectOut:
     """The MAP outer loop on the device; synchronizes to read the result."""
     dev = csr.row_ptr.device
-    acc = torch.as_tensor(accepting0, dtype=torch.uint8).to(dev).contiguous()
-    res = new_result(dev)
-    trace = torch.zeros((trace_cap, 3), dtype=torch.int64, device=dev) if trace_cap > 0 else None
-    acc_out = torch.zeros(csr.n, dtype=torch.uint8, device=dev) if want_acc else None
-    if ws is None:
-        ws = workspace(csr.n, csr.m, flags, device=dev)
-    _check(map_detect(csr.n, csr.row_ptr, csr.col, csr.rrow_ptr, csr.rcol, acc, res, trace, acc_out,
-                      max_iterations, flags, ws, stream), "map_detect")
-    r = Result.from_tensor(res)
-    tr = None
-    if trace is not None:
-        tr = trace.cpu().numpy().view(np.uint64)[:min(r.iterations, trace_cap)].copy()
-    return DetectOut(r, tr, acc_out.cpu().numpy() if acc_out is not None else None)
+    with _on(stream):
+        acc = torch.as_tensor(accepting0, dtype=torch.uint8).to(dev).contiguous()
+        res = new_result(dev)
+        trace = torch.zeros((trace_cap, 3), dtype=torch.int64, device=dev) if trace_cap > 0 else None
+        acc_out = torch.zeros(csr.n, dtype=torch.uint8, device=dev) if want_acc else None
+        if ws is None:
+            ws = workspace(csr.n, csr.m, flags, device=dev)
+        _check(map_detect(csr.n, csr.row_ptr, csr.col, csr.rrow_ptr, csr.rcol, acc, res, trace, acc_out,
+                          max_iterations, flags, ws, stream), "map_detect")
+        r = Result.from_tensor(res)
+        tr = None
+        if trace is not None:
+            tr = trace.cpu().numpy().view(np.uint64)[:min(r.iterations, trace_cap)].copy()
+        return DetectOut(r, tr, acc_out.cpu().numpy() if acc_out is not None else None)
 
 
 @dataclass
@@ -302,15 +315,17 @@ def lasso(csr: Csr, witness: int, init: int = 0, cap: int | None = None, ws=None
     """Counterexample for ``witness``: shortest path from ``init`` (0: none), shortest cycle through it."""
     dev = csr.row_ptr.device
     cap = 2 * csr.n + 1 if cap is None else cap
-    path = torch.zeros(max(cap, 1), dtype=torch.int32, device=dev)
-    res = torch.zeros(8, dtype=torch.int32, device=dev)
-    if ws is None:
-        ws = workspace(csr.n, csr.m, device=dev)
-    _check(map_lasso(csr.n, csr.row_ptr, csr.col, witness, init, path[:cap], res, ws, stream), "map_lasso")
-    a = res.cpu().numpy()
-    status, s, c, plen = (int(x) for x in a[:4])
-    scanned = int(a[4:6].view(np.int64)[0])
-    return LassoOut(status, s, c, path[:plen].cpu().numpy() if status == MAP_OK else None, scanned, int(a[6]))
+    with _on(stream):
+        path = torch.zeros(max(cap, 1), dtype=torch.int32, device=dev)
+        res = torch.zeros(8, dtype=torch.int32, device=dev)
+        if ws is None:
+            ws = workspace(csr.n, csr.m, device=dev)
+        _check(map_lasso(csr.n, csr.row_ptr, csr.col, witness, init, path[:cap], res, ws, stream), "map_lasso")
+        a = res.cpu().numpy()
+        status, s, c, plen = (int(x) for x in a[:4])
+        scanned = int(a[4:6].view(np.int64)[0])
+        return LassoOut(status, s, c, path[:plen].cpu().numpy() if status == MAP_OK else None, scanned,
+                        int(a[6]))
 
 
 @dataclass
@@ -328,18 +343,19 @@ def trim(csr: Csr, accepting=None, ws=None, stream=None, sync: bool = True) -> T
     if csr.rrow_ptr is None:
         raise ValueError("trim needs the transposed CSR (build_csr(..., transposed=True))")
     dev = csr.row_ptr.device
-    acc = None if accepting is None else torch.as_tensor(accepting, dtype=torch.uint8).to(dev).contiguous()
-    keep = torch.empty(csr.n, dtype=torch.uint8, device=dev)
-    acc_out = torch.empty(csr.n, dtype=torch.uint8, device=dev) if acc is not None else None
-    res = torch.zeros(4, dtype=torch.int32, device=dev)
-    if ws is None:
-        ws = workspace(csr.n, csr.m, device=dev)
-    _check(map_trim(csr.n, csr.row_ptr, csr.col, csr.rrow_ptr, csr.rcol, acc, keep, acc_out, res, ws, stream),
-           "map_trim")
-    if not sync:
-        return TrimOut(0, -1, -1, -1, keep, acc_out)
-    a = res.cpu().numpy()
-    return TrimOut(int(a[0]), int(a[1]), int(a[2]), int(a[3]), keep, acc_out)
+    with _on(stream):
+        acc = None if accepting is None else torch.as_tensor(accepting, dtype=torch.uint8).to(dev).contiguous()
+        keep = torch.empty(csr.n, dtype=torch.uint8, device=dev)
+        acc_out = torch.empty(csr.n, dtype=torch.uint8, device=dev) if acc is not None else None
+        res = torch.zeros(4, dtype=torch.int32, device=dev)
+        if ws is None:
+            ws = workspace(csr.n, csr.m, device=dev)
+        _check(map_trim(csr.n, csr.row_ptr, csr.col, csr.rrow_ptr, csr.rcol, acc, keep, acc_out, res, ws,
+                        stream), "map_trim")
+        if not sync:
+            return TrimOut(0, -1, -1, -1, keep, acc_out)
+        a = res.cpu().numpy()
+        return TrimOut(int(a[0]), int(a[1]), int(a[2]), int(a[3]), keep, acc_out)
 
 
 # ------------------------------------------------------------------ batches
@@ -372,13 +388,17 @@ class Batch:
             raise MapError(MAP_ERANGE, "map_batch_workspace_bytes")
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.flags = flags
+        self.stream = None   # stream of the last launch (None: torch's current stream)
 
     def launch(self, stream=None):
         _check(map_detect_batch(self.count, self.desc, self.gang, self.results, self.total_n, self.flags, self.ws,
                                 stream), "map_detect_batch")
+        self.stream = stream
 
     def read(self):
-        host = self.results.cpu()
+        """Results of the last launch (read on its stream, so they are final)."""
+        with _on(self.stream):
+            host = self.results.cpu()
         return [Result.from_tensor(host[i]) for i in range(self.count)]
 
 
