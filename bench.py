@@ -544,8 +544,9 @@ def main():
     ws = mc.workspace(n, m, device=dev)
     row_ptr = torch.empty(n + 1, dtype=torch.int32, device=dev)
     col = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
-    rrow_ptr = torch.empty(n + 1, dtype=torch.int32, device=dev)
-    rcol = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    # The transposed CSR is built only where the path reads it (frontier rounds).
+    rrow_ptr = torch.empty(n + 1, dtype=torch.int32, device=dev) if args.push else None
+    rcol = torch.empty(max(m, 1), dtype=torch.int32, device=dev) if args.push else None
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     res = mc.new_result(dev)
     stream = torch.cuda.current_stream()

@@ -2255,17 +2255,54 @@ __global__ void fill_u32(uint32_t* p, int64_t count, uint32_t val) {
     p[i] = val;
 }
 
-// Degree histogram of the key endpoint: cnt[key] += 1 (cnt = row_ptr, so row
-// v's count lands at index v+1 for 1-based key v+1).
+// Runs of equal keys among a wave's 64 consecutive edges.  Edge lists in
+// generation order come grouped by source, so one atomic per run instead of
+// one per edge takes most of the atomic traffic out of the build; on lists in
+// random order nearly every run has length 1 and nothing changes.  A run
+// starts at a valid lane whose key differs from the previous lane's (or whose
+// previous lane is invalid, or at lane 0) and ends before the next start or
+// invalid lane.  All 64 lanes must call it (the wave walks the edges in
+// wave-aligned steps).
+struct KeyRun {
+  bool head;  // this lane starts a run
+  int len;    // head: lanes in the run
+  int first;  // valid lane: the lane that starts its run
+};
+
+__device__ __forceinline__ KeyRun key_run(bool valid, int32_t k, int lane) {
+  const int32_t pk = __shfl_up(k, 1, kWave);
+  const int pv = __shfl_up(valid ? 1 : 0, 1, kWave);
+  const bool head = valid && (lane == 0 || pv == 0 || pk != k);
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long stops = heads | ~__ballot(valid);
+  const unsigned long long upto = (2ull << lane) - 1ull;  // lanes 0..lane (all 64 for lane 63)
+  const unsigned long long after = stops & ~upto;
+  KeyRun r;
+  r.head = head;
+  r.len = (after ? __builtin_ctzll(after) : kWave) - lane;
+  const unsigned long long before = heads & upto;
+  r.first = before ? 63 - __builtin_clzll(before) : lane;
+  return r;
+}
+
+// Degree histogram of the key endpoint: cnt[key] += (edges with that key)
+// (cnt = row_ptr, so row v's count lands at index v+1 for 1-based key v+1).
 __global__ void csr_hist(int32_t n, int64_t m, const int32_t* __restrict__ key, const int32_t* __restrict__ other,
                          int32_t* cnt, int32_t* status) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-    int32_t k = key[i], o = other[i];
-    if (k < 1 || k > n || o < 1 || o > n) {
-      __hip_atomic_store(status, (int32_t)MAP_ERANGE_DEV, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      continue;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t w0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); w0 < m; w0 += stride) {
+    const int64_t i = w0 + lane;
+    int32_t k = 0;
+    bool valid = false;
+    if (i < m) {
+      const int32_t o = other[i];
+      k = key[i];
+      valid = k >= 1 && k <= n && o >= 1 && o <= n;
+      if (!valid) __hip_atomic_store(status, (int32_t)MAP_ERANGE_DEV, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    atomicAdd(&cnt[k], 1);
+    const KeyRun r = key_run(valid, k, lane);
+    if (r.head) atomicAdd(&cnt[k], r.len);
   }
 }
 
@@ -2333,14 +2370,26 @@ __global__ void copy_i32(int32_t* dst, const int32_t* src, int64_t count) {
     dst[i] = src[i];
 }
 
-// col[cursor[key-1]++] = other-1 for every in-range edge.
+// col[cursor[key-1]++] = other-1 for every in-range edge; a run of equal keys
+// reserves its slots with one atomic and fills them in edge order.
 __global__ void csr_scatter(int32_t n, int64_t m, const int32_t* __restrict__ key, const int32_t* __restrict__ other,
                             int32_t* cursor, int32_t* col) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-    int32_t k = key[i], o = other[i];
-    if (k < 1 || k > n || o < 1 || o > n) continue;
-    int32_t pos = atomicAdd(&cursor[k - 1], 1);
-    col[pos] = o - 1;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t w0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); w0 < m; w0 += stride) {
+    const int64_t i = w0 + lane;
+    int32_t k = 0, o = 0;
+    bool valid = false;
+    if (i < m) {
+      k = key[i];
+      o = other[i];
+      valid = k >= 1 && k <= n && o >= 1 && o <= n;
+    }
+    const KeyRun r = key_run(valid, k, lane);
+    int32_t pos = 0;
+    if (r.head) pos = atomicAdd(&cursor[k - 1], r.len);
+    pos = __shfl(pos, r.first, kWave) + (lane - r.first);
+    if (valid) col[pos] = o - 1;
   }
 }
 

@@ -272,6 +272,77 @@ def test_csr_build_matches_edge_list(mc):
         assert np.array_equal(got, want)
 
 
+def _check_csr(csr, n, src, dst, orientations=2):
+    """Both CSRs hold exactly the in-range edges (ids 1..n at both ends)."""
+    ok = (src >= 1) & (src <= n) & (dst >= 1) & (dst <= n)
+    src, dst = src[ok], dst[ok]
+    pairs = ((csr.row_ptr, csr.col, src, dst), (csr.rrow_ptr, csr.rcol, dst, src))[:orientations]
+    for rp, col, key, other in pairs:
+        rp = rp.cpu().numpy()
+        deg = np.bincount(key - 1, minlength=n)
+        assert rp[0] == 0 and np.array_equal(np.diff(rp), deg)
+        col = col.cpu().numpy()[:len(key)]
+        rows = np.repeat(np.arange(n), deg)
+        got = np.sort(rows.astype(np.int64) * n + col)
+        want = np.sort((key.astype(np.int64) - 1) * n + (other - 1))
+        assert np.array_equal(got, want)
+
+
+def _grouped(rng, n, max_deg, m_cap=None):
+    """Edges grouped by source (generation order), degrees 0..max_deg."""
+    deg = rng.integers(0, max_deg + 1, n)
+    src = np.repeat(np.arange(1, n + 1, dtype=np.int32), deg)
+    if m_cap is not None:
+        src = src[:m_cap]
+    dst = rng.integers(1, n + 1, len(src)).astype(np.int32)
+    return src, dst
+
+
+@pytest.mark.parametrize("case", ["random", "grouped", "hub", "ragged", "invalid"])
+def test_csr_build_key_runs(mc, case):
+    """Edges with equal keys share one atomic per run of a wave: runs that
+    cross wave boundaries, runs broken by out-of-range edges, lists in random
+    order, a vertex whose edges fill many waves, a ragged tail."""
+    rng = np.random.default_rng({"random": 11, "grouped": 12, "hub": 13, "ragged": 14, "invalid": 15}[case])
+    n = 4000
+    if case == "random":
+        src = rng.integers(1, n + 1, 50_000).astype(np.int32)
+        dst = rng.integers(1, n + 1, 50_000).astype(np.int32)
+        src[1000:1100] = 7                       # one run among random keys
+    elif case == "grouped":
+        src, dst = _grouped(rng, n, 200)
+    elif case == "hub":
+        src, dst = _grouped(rng, n, 8)
+        src = np.concatenate([src[:5000], np.full(70_000, 123, np.int32), src[5000:]])
+        dst = np.concatenate([dst[:5000], rng.integers(1, n + 1, 70_000).astype(np.int32), dst[5000:]])
+    elif case == "ragged":
+        src, dst = _grouped(rng, n, 90, m_cap=64 * 1000 + 37)
+    else:
+        src, dst = _grouped(rng, n, 150)
+        bad = rng.choice(len(src), 300, replace=False)
+        src[bad[:100]] = 0
+        src[bad[100:200]] = n + 1
+        dst[bad[200:]] = -3
+    print("csr runs", case, "n", n, "m", len(src), flush=True)
+    csr = mc.build_csr(n, src, dst)
+    status = int(csr.status.item())
+    assert status == (mc.MAP_ERANGE_DEV if case == "invalid" else 0)
+    _check_csr(csr, n, src, dst)
+
+
+def test_csr_build_grid_stride(mc):
+    """More edges than one pass of the launch covers (65,536 workgroups of 256
+    threads), grouped by source, so runs also cross the stride boundary."""
+    rng = np.random.default_rng(16)
+    n = 1 << 20
+    src, dst = _grouped(rng, n, 40)
+    assert len(src) > 65536 * 256
+    print("csr grid stride n", n, "m", len(src), flush=True)
+    csr = mc.build_csr(n, src, dst, transposed=False)
+    assert int(csr.status.item()) == 0
+    _check_csr(csr, n, src, dst, orientations=1)
+
+
 def test_csr_build_range_error(mc):
     import torch
     n = 10
