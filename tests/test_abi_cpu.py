@@ -166,3 +166,29 @@ def test_engine_host_side_errors_without_device(lib):
     assert lib.map_engine_workgroups(None) == 0
     assert lib.map_strerror(-7).decode().startswith("engine")
     assert lib.map_strerror(1).decode() == "job not finished yet"
+
+
+def test_import_fails_without_the_library(tmp_path):
+    """The binding has no fallback: a copy of the package without
+    libmapcheck.so refuses to import."""
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "paper_0912_2555_amd"
+    pkg.mkdir()
+    shutil.copy(os.path.join(ROOT, "paper_0912_2555_amd", "__init__.py"), pkg / "__init__.py")
+    r = subprocess.run([sys.executable, "-c", "import paper_0912_2555_amd"], cwd=tmp_path, capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "libmapcheck.so" in r.stderr
+
+
+def test_product_code_does_not_use_the_oracle():
+    """Only tests, the smoke check and the bench's CPU baseline may call the
+    oracle: the package and its sources never name it."""
+    pkg = os.path.join(ROOT, "paper_0912_2555_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".c", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"\bimport\s+oracle\b|\bfrom\s+oracle\b|map_oracle", text), f
