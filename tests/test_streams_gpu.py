@@ -91,3 +91,38 @@ def test_two_streams_at_once(mc):
         assert r.verdict == ref.verdict
         assert r.accepting_left == ref.accepting_left
         assert np.array_equal(acc_out.cpu().numpy(), ref.acc_out)
+
+
+def test_two_host_threads(mc):
+    """Two host threads, each on its own stream, build and detect at the same
+    time (the binding releases the interpreter lock during library calls)."""
+    import threading
+
+    import torch
+    graphs = [synth.config2(seed=5, n=1 << 16, planted=True), synth.config2(seed=9, n=1 << 15)]
+    refs = [oracle.map_detect(g) for g in graphs]
+    out = [None, None]
+    errors = []
+
+    def work(i):
+        try:
+            torch.cuda.set_device(0)
+            s = torch.cuda.Stream()
+            g = graphs[i]
+            csr = mc.build_csr(g.n, g.src, g.dst, transposed=False, stream=s)
+            out[i] = mc.detect(csr, g.acc, want_acc=True, stream=s)
+        except Exception as e:  # reported below, in the test's own thread
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=100)
+    assert not any(t.is_alive() for t in threads), "a worker thread did not finish"
+    assert not errors, errors
+    for g, o, ref in zip(graphs, out, refs):
+        say("  thread", g.name, "verdict", o.result.verdict, "oracle", ref.verdict)
+        assert o.result.status == 0
+        assert o.result.verdict == ref.verdict
+        assert np.array_equal(o.accepting_out, ref.acc_out)
