@@ -38,9 +38,8 @@
  *     run concurrently; the library holds no mutable state besides a per-
  *     device cache of launch limits.
  *   - map_propagate, map_detect, map_lasso, map_trim, map_engine_create and
- *     map_detect_batch (with gangs of more than one workgroup) start their
- *     kernels with a cooperative launch (the workgroups wait for one
- *     another).  The HIP runtime may hold such a launch until an earlier one
+ *     map_detect_batch (when given a gang array) start their kernels with a
+ *     cooperative launch (the workgroups wait for one another).  The HIP runtime may hold such a launch until an earlier one
  *     on the device has ended; and while one process makes cooperative
  *     launches, another process's cooperative launch on the same device has
  *     been refused, which the call reports as MAP_EDEVICE.
