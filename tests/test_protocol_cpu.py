@@ -172,3 +172,145 @@ def test_planted_mistake_is_caught(mistake):
         sh = run(n, succ, acc, nb, s, **{mistake: True})
         wrong += sh.val != want
     assert wrong > 0
+
+
+# ----------------------------------------------------- two outer iterations
+#
+# Packed words carry the iteration parity: a word of the other parity reads
+# as 0, and the first sweep of an iteration (the reset) takes what the
+# accepting successors send (their ids) instead of reading values.  The model
+# runs iteration 1 to its fixpoint, strips, and starts iteration 2 on the
+# words iteration 1 left (blocks begin their resets at different times).
+
+def block_iter(b, rows, succ, acc, sh, tag, par, ignore_parity=False):
+    def sent(word, w):
+        p, a, m = word
+        if p != par and not ignore_parity:
+            return 0
+        return max(m, w + 1) if a else m
+
+    own = {}
+    d_seen = None
+    first = True
+    while True:
+        if not first:
+            while True:
+                if sh.done == tag:
+                    return
+                d = sh.dirty
+                yield
+                if d != d_seen:
+                    break
+                if b == 0:
+                    want = (tag, d + 1)
+                    if all(q == want for q in sh.quiet):
+                        yield
+                        if sh.dirty == d:
+                            sh.done = tag
+                            return
+                yield
+        d0 = sh.dirty
+        yield
+        changed = False
+        for v in rows:
+            if first:
+                best = 0
+                for w in succ[v]:
+                    best = max(best, (w + 1) if acc[w] else 0)
+                    yield
+                own[v] = (par, acc[v], best)
+                changed |= best != 0 or acc[v]
+                continue
+            best = own[v][2]
+            for w in succ[v]:
+                x = sent(own[w], w) if w in own else sent(sh.val[w], w)
+                yield
+                best = max(best, x)
+            if best > own[v][2]:
+                own[v] = (par, own[v][1], best)
+                changed = True
+        if first and not changed:
+            # The reset writes every row; new words of value 0 read as the
+            # stale ones do (0), so nothing needs announcing.
+            for v in rows:
+                sh.val[v] = own[v]
+        first = False
+        if changed:
+            for v in rows:
+                sh.val[v] = own[v]
+            yield
+            sh.dirty += 1
+            d_seen = None
+        else:
+            sh.quiet[b] = (tag, d0 + 1)
+            d_seen = d0
+        yield
+
+
+def run_iter(sh, n, succ, acc, nb, seed, tag, ignore_parity=False):
+    rng = random.Random(seed)
+    cuts = [round(i * n / nb) for i in range(nb + 1)]
+    par = tag & 1
+    gens = [block_iter(b, list(range(cuts[b], cuts[b + 1])), succ, acc, sh, tag, par, ignore_parity)
+            for b in range(nb)]
+    live = list(range(nb))
+    steps = 0
+    while live:
+        i = rng.choice(live)
+        try:
+            next(gens[i])
+        except StopIteration:
+            live.remove(i)
+        steps += 1
+        assert steps < 2_000_000, "the model did not terminate"
+    assert all(p == par for (p, _, _) in sh.val), "a row missed its reset"
+    return [m for (_, _, m) in sh.val]
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_second_iteration_reads_stale_words_as_zero(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(3, 14))
+    nb = int(rng.integers(2, min(n, 5) + 1))
+    succ, acc1 = random_graph(rng, n, 3, 0.4)
+    want1 = least_fixpoint(n, succ, acc1)
+    # the strip between the iterations: every accepting vertex that is some
+    # vertex's map value loses its flag
+    acc2 = list(acc1)
+    for m in want1:
+        if m:
+            acc2[m - 1] = False
+    want2 = least_fixpoint(n, succ, acc2)
+    for s in range(4):
+        sh = Shared(n, nb)
+        sh.val = [(0, False, 0)] * n
+        sh.done = 0
+        got1 = run_iter(sh, n, succ, acc1, nb, seed * 10 + s, 1)
+        assert got1 == want1
+        sh.quiet = [None] * nb
+        got2 = run_iter(sh, n, succ, acc2, nb, seed * 10 + s + 5, 2)
+        assert got2 == want2, (seed, s)
+
+
+def test_planted_parity_slip_is_caught():
+    """Reading a word of the previous iteration as a value lets stale values
+    into the next fixpoint in some interleaving."""
+    wrong = 0
+    for seed in range(60):
+        rng = np.random.default_rng(2000 + seed)
+        n = int(rng.integers(4, 14))
+        nb = int(rng.integers(2, min(n, 5) + 1))
+        succ, acc1 = random_graph(rng, n, 3, 0.4)
+        want1 = least_fixpoint(n, succ, acc1)
+        acc2 = list(acc1)
+        for m in want1:
+            if m:
+                acc2[m - 1] = False
+        want2 = least_fixpoint(n, succ, acc2)
+        sh = Shared(n, nb)
+        sh.val = [(0, False, 0)] * n
+        sh.done = 0
+        run_iter(sh, n, succ, acc1, nb, seed, 1)
+        sh.quiet = [None] * nb
+        wrong += run_iter(sh, n, succ, acc2, nb, seed + 7, 2, ignore_parity=True) != want2
+    assert wrong > 0
