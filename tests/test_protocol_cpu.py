@@ -1,5 +1,6 @@
-"""A model of the asynchronous fixpoint control of the loop kernel, run under
-random interleavings on the CPU (no GPU, no library).
+"""Models of the loop kernel's cross-workgroup protocols (the asynchronous
+fixpoint control, the iteration parity of packed words, the barrier reduction
+sets), run under random interleavings on the CPU (no GPU, no library).
 
 The model follows the kernel's protocol step by step:
 
@@ -314,3 +315,56 @@ def test_planted_parity_slip_is_caught():
         sh.quiet = [None] * nb
         wrong += run_iter(sh, n, succ, acc2, nb, seed + 7, 2, ignore_parity=True) != want2
     assert wrong > 0
+
+
+# ------------------------------------------------- barrier reduction epochs
+#
+# Counts reduced at a grid barrier go to one of three sets: epoch E adds into
+# set E % 3; after barrier E every block reads set E % 3 (before it arrives at
+# barrier E + 1); block 0 then clears set (E + 2) % 3, the one read during
+# epoch E - 1 and next written in epoch E + 2.  The model checks every read
+# sum under random interleavings, and that clearing the set of the next epoch
+# instead is caught.
+
+def reducer(b, nb, epochs, contrib, sh, clear_next):
+    for e in range(epochs):
+        sh.sets[e % 3] += contrib[b][e]             # atomic add
+        yield
+        sh.arrived[e] += 1                          # arrive at barrier e
+        while sh.arrived[e] < nb:
+            yield
+        if b == 0:
+            sh.sets[((e + 1) if clear_next else (e + 2)) % 3] = 0
+        yield
+        sh.reads.append((e, sh.sets[e % 3]))        # the reduced value
+        yield
+
+
+@pytest.mark.parametrize("clear_next", [False, True])
+def test_barrier_reduction_sets(clear_next):
+    wrong = 0
+    for seed in range(200):
+        rng = random.Random(seed)
+        nb, epochs = rng.randint(2, 5), 6
+        contrib = [[rng.randint(0, 9) for _ in range(epochs)] for _ in range(nb)]
+        want = [sum(contrib[b][e] for b in range(nb)) for e in range(epochs)]
+
+        class S:
+            pass
+        sh = S()
+        sh.sets = [0, 0, 0]
+        sh.arrived = [0] * epochs
+        sh.reads = []
+        gens = [reducer(b, nb, epochs, contrib, sh, clear_next) for b in range(nb)]
+        live = list(range(nb))
+        while live:
+            i = rng.choice(live)
+            try:
+                next(gens[i])
+            except StopIteration:
+                live.remove(i)
+        wrong += any(v != want[e] for e, v in sh.reads)
+    if clear_next:
+        assert wrong > 0
+    else:
+        assert wrong == 0
