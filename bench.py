@@ -13,9 +13,20 @@ strips nothing, 1276 iterations).
 Printed: one JSON line.  value = K * E / (step time) in GTEPS, K the number of
 fixpoint computations and E the edge count: one traversal of every edge per
 iteration, the least work any exact fixpoint needs.  The roofline object
-prices the persistent loop kernel (the dominant kernel) at its algorithmic
-bytes per launch: sweeps * (4(N+1) + 4E + 8N + N/8) + K * 4N, over its average
-launch time measured with HIP events on the launch stream.
+prices the persistent loop kernel (the dominant kernel) at the method's bytes
+per launch, K * (4E + 8N) (one pass over the column indices and row offsets
+and one write of the map vector per fixpoint computation), over its average
+launch time measured with HIP events on the launch stream; its `dense_equiv`
+member prices the sweeps the schedule actually made as dense passes,
+sweeps * (4(N+1) + 4E + 8N + N/8) + K * 4N, with sweeps counted over all
+workgroups (their total over the number of workgroups).
+
+The default line also carries `batched`: the first graphs of the config-4
+batch solved in one persistent launch against the plain per-graph loop
+(graphs/s, each verdict against the oracle's golden), and `cpu_baseline` with
+its legs: the oracle's exact sequential route on one core (the headline
+value), and the paper's propagation (jacobi) on one core and on all host
+cores, on bounded samples of the same workload.
 """
 from __future__ import annotations
 
@@ -68,6 +79,24 @@ def sweep_bytes(n, m):
     return 4 * (n + 1) + 4 * m + 8 * n + (n + 7) // 8
 
 
+def method_bytes(n, m, k):
+    """The method's minimum bytes for K fixpoint computations: per computation one
+    pass over the CSR (4E column indices, 4N row offsets) and one write of map (4N)."""
+    return k * (4 * m + 8 * n)
+
+
+def host_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0))}
+
+
 def golden_for(key):
     path = os.path.join(ROOT, "tests", "golden", "full_size.json")
     try:
@@ -76,27 +105,59 @@ def golden_for(key):
         return None
 
 
-def cpu_baseline(g, key, budget_s=20.0):
-    """The oracle (single-threaded C, as it stands) on a bounded sample."""
+def _oracle_leg(g, mode, budget_s, omp=False, iters=None):
+    """GTEPS_alg of the oracle's MAP loop on the first outer iterations that fit the budget."""
     import oracle
-    probe = 5
+    if iters is None:
+        probe = 1 if mode == "jacobi" else 5
+        t = time.perf_counter()
+        oracle.map_detect(g, mode=mode, max_iterations=probe, omp=omp)
+        per = (time.perf_counter() - t) / probe
+        iters = int(max(probe, min(10_000, budget_s / max(per, 1e-6))))
     t = time.perf_counter()
-    oracle.map_detect(g, mode="desc", max_iterations=probe)
-    per = (time.perf_counter() - t) / probe
-    iters = int(max(probe, min(10_000, budget_s / max(per, 1e-6))))
-    t = time.perf_counter()
-    d = oracle.map_detect(g, mode="desc", max_iterations=iters)
+    d = oracle.map_detect(g, mode=mode, max_iterations=iters, omp=omp)
     dt = time.perf_counter() - t
-    k = d.iterations
-    return {
-        "value": round(k * g.m / dt / 1e9, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+    return d.iterations, dt, round(d.iterations * g.m / dt / 1e9, 6)
+
+
+def cpu_baseline(g, key, budget_s=12.0, jacobi_budget_s=6.0):
+    """The oracle (C, as it stands) on bounded samples: the exact sequential route
+    on one core (the value), and the jacobi route on one core and on every
+    host thread (the OpenMP build of the same source)."""
+    import oracle
+    k, dt, v = _oracle_leg(g, "desc", budget_s)
+    out = {
+        "value": v, "unit": "GTEPS", "cores": 1, "kind": "oracle",
         "sample": f"first {k} outer iterations of {key} (of the full run), oracle 'desc' fixpoint, "
                   f"{dt:.1f} s wall on the host",
+        "host": host_info(),
     }
+    kj, dtj, vj = _oracle_leg(g, "jacobi", jacobi_budget_s)
+    kjo, dtjo, vjo = _oracle_leg(g, "jacobi", 0, omp=True, iters=kj)
+    out["legs"] = [
+        {"route": "desc", "cores": 1, "value": v, "unit": "GTEPS", "iterations": k, "seconds": round(dt, 3)},
+        {"route": "jacobi", "cores": 1, "value": vj, "unit": "GTEPS", "iterations": kj, "seconds": round(dtj, 3)},
+        {"route": "jacobi", "cores": oracle.threads(omp=True), "value": vjo, "unit": "GTEPS", "iterations": kjo,
+         "seconds": round(dtjo, 3), "build": "OpenMP"},
+    ]
+    return out
 
 
 def bench_batch(args):
     """Batched MAP over the config-4 graphs: graphs/s batched vs the plain loop."""
+    figures = batch_run(args, args.batch_count)
+    out = {
+        "metric": METRIC, "value": figures.pop("graphs_per_s"), "unit": "graphs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": figures.pop("ms_per_step"),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": figures.pop("config"), **figures,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def batch_run(args, count, capture=True):
+    """The first `count` config-4 graphs: one persistent launch (tuned gang policy)
+    against the plain per-graph loop; returns the figures."""
     import torch
     import paper_0912_2555_amd as mc
     from paper_0912_2555_amd import autotune
@@ -104,7 +165,6 @@ def bench_batch(args):
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    count = args.batch_count
     t0 = time.perf_counter()
     csrs, accs, ns, ms = [], [], [], []
     ws = None
@@ -161,18 +221,21 @@ def bench_batch(args):
     # the one-workgroup-per-graph launch captured in a HIP graph, replayed
     t_graph = None
     graph_ok = None
-    bg = make(None)
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
-        bg.launch(stream=s)
-    torch.cuda.current_stream().wait_stream(s)
-    torch.cuda.synchronize()
-    cg = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(cg):
-        bg.launch()
-    graph_ok = True
-    reps = max(1, args.steps)
+    bg = make(None) if capture else None
+    if bg is None:
+        reps = 0
+    else:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            bg.launch(stream=s)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        cg = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(cg):
+            bg.launch()
+        graph_ok = True
+        reps = max(1, args.steps)
     for r in range(reps):
         bg.results.zero_()           # eager work between replays
         torch.cuda.synchronize()
@@ -187,16 +250,16 @@ def bench_batch(args):
                          and y.status == 0 for x, y in zip(res_b, plain))
     gold_path = os.path.join(ROOT, "tests", "golden", "batch_c4.json")
     exact_vs_oracle = None
-    if os.path.exists(gold_path) and count == 4096:
+    if os.path.exists(gold_path) and count <= 4096:
         gold = json.load(open(gold_path))["verdicts"]
         exact_vs_oracle = all([r.found, r.witness, r.iterations, r.accepting_left] == gold[i]
                               for r, i in zip(res_b, order))
     work = sum(r.iterations * m for r, m in zip(res_b, o_ms))
-    out = {
-        "metric": METRIC, "value": round(count / t_batch, 2), "unit": "graphs/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_batch * 1e3, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": WORKLOADS["c4"][0], "key": "c4", "graphs": count, "sum_n": int(sum(ns)),
+    return {
+        "graphs_per_s": round(count / t_batch, 2), "ms_per_step": round(t_batch * 1e3, 3),
+        "config": {"workload": WORKLOADS["c4"][0] if count == 4096 else
+                   f"the first {count} of the 4,096 config-4 graphs", "key": "c4", "graphs": count,
+                   "sum_n": int(sum(ns)),
                    "sum_m": int(sum(ms)), "parallelism": "single GPU", "order": "largest first",
                    "gang_policy": autotune.policy_name(policy)},
         "plain_graphs_per_s": round(count / t_plain, 2), "plain_ms": round(t_plain * 1e3, 3),
@@ -208,7 +271,6 @@ def bench_batch(args):
         "exact_vs_plain": exact_vs_plain, "exact_vs_oracle_golden": exact_vs_oracle,
         "found": int(sum(r.found for r in res_b)),
     }
-    print(json.dumps(out), flush=True)
 
 
 def bench_serve(args):
@@ -496,11 +558,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2B", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--sync-sweeps", action="store_true", help="grid barrier after every sweep")
     ap.add_argument("--stream", action="store_true", help="stream the CSR every sweep (no on-chip staging)")
     ap.add_argument("--push", action="store_true", help="frontier rounds over the transposed CSR")
     ap.add_argument("--batch-count", type=int, default=4096, help="graphs in the config-4 batch")
+    ap.add_argument("--line-batch", type=int, default=512,
+                    help="single-graph line: also run the first N config-4 graphs batched vs plain (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a plain copy of known size and exit")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--serve-count", type=int, default=1000, help="queries in the config-5 stream")
@@ -583,8 +647,10 @@ def main():
     detect_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
     k = r.iterations
     gteps = k * m / (ms_step * 1e-3) / 1e9
-    alg_bytes = r.sweeps * sweep_bytes(n, m) + k * 4 * n
+    alg_bytes = method_bytes(n, m, k)
     achieved = alg_bytes / (detect_ms * 1e-3) / 1e9
+    dense_bytes = r.sweeps * sweep_bytes(n, m) + k * 4 * n
+    dense_gbs = dense_bytes / (detect_ms * 1e-3) / 1e9
     traffic = counted_traffic(args.workload, flags)
     gold = golden_for(args.workload)
     exact = None
@@ -606,8 +672,16 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "traffic_gbs": round(traffic / (detect_ms * 1e-3) / 1e9, 2) if traffic else None,
-                     "bytes_per_launch": int(alg_bytes)},
+                     "bytes_per_launch": int(alg_bytes), "accounting": "method: K*(4E+8N) per launch",
+                     "dense_equiv": {"achieved": round(dense_gbs, 2), "frac": round(dense_gbs / HBM_PEAK_GBS, 4),
+                                     "bytes_per_launch": int(dense_bytes),
+                                     "accounting": "whole-graph sweeps * (4(N+1)+4E+8N+N/8) + K*4N per launch"}},
     }
+    if args.line_batch > 0:
+        torch.cuda.synchronize()
+        del ws, row_ptr, col, src, dst
+        torch.cuda.empty_cache()
+        out["batched"] = batch_run(args, args.line_batch, capture=False)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, args.workload, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -26,7 +26,11 @@
  *     serving engine (map_engine_create allocates its own queue and control
  *     state, map_engine_destroy frees them) the library never allocates or
  *     frees memory; scratch comes from the caller's workspace `ws` of at least
- *     map_workspace_bytes(n, m, flags) bytes, 256-byte aligned.
+ *     map_workspace_bytes(n, m, flags) bytes, 256-byte aligned.  Its contents
+ *     need no initialisation; one word of it (the iteration-tag epoch of the
+ *     packed values) carries over from one map_propagate / map_detect call to
+ *     the next on the same workspace, so that values left by an earlier call
+ *     never carry a tag of the new call's first iterations.
  *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Every
  *     call only enqueues work on it and returns; nothing synchronizes.  Device
  *     outputs are valid once the stream has been synchronized.
@@ -88,7 +92,9 @@ typedef struct map_result {
   int32_t witness;        /* largest id v with map(v) == v in the last iteration, else 0 */
   int32_t iterations;     /* K: number of fixpoint computations made */
   int32_t status;         /* MAP_OK, MAP_ENOTCONVERGED */
-  int64_t sweeps;         /* propagation sweeps over all iterations (schedule dependent) */
+  int64_t sweeps;         /* whole-graph propagation sweeps over all iterations: the sum of
+                             every workgroup's sweeps over the number of workgroups, rounded
+                             (schedule dependent; in barrier mode every workgroup's count) */
   int32_t accepting_left; /* number of accepting vertices at exit */
   int32_t reserved;
 } map_result;
@@ -149,7 +155,8 @@ int map_propagate(int32_t n, const int32_t *row_ptr, const int32_t *col, const i
  *   result         device map_result out.
  *   trace          device uint64[trace_cap][3] out, or NULL: row k-1 holds
  *                  { |Del_k| (flags removed after iteration k; 0 when it found a
- *                  cycle or removed none), sweeps of iteration k, digest of
+ *                  cycle or removed none), whole-graph sweeps of iteration k
+ *                  (counted as in map_result.sweeps), digest of
  *                  map_k = sum over v of mix64((v << 32) | map_k(v)) mod 2^64,
  *                  mix64 the SplitMix64 finalizer }.  Rows beyond trace_cap are
  *                  dropped.

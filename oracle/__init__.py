@@ -37,31 +37,49 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
 _SRC = os.path.join(_HERE, "map_oracle.c")
 MODES = {"jacobi": 0, "reach": 1, "desc": 2}
+_BASE_FLAGS = ["-O2", "-std=gnu11", "-fPIC", "-shared", "-Wall"]
+# Build flavours of the same source: the plain single-threaded oracle, and the
+# OpenMP one (the jacobi pass's edge loop shared among the host's threads),
+# used only to time the jacobi route on all host cores.
+_FLAVOURS = {_LIB_PATH: [], _OMP_PATH: ["-fopenmp", "-DORACLE_OPENMP"]}
 
 
 def build(force: bool = True) -> str:
-    """Compile ``liboracle.so`` next to this file with gcc (single-threaded C)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
-                               "-o", tmp, _SRC])
-        os.replace(tmp, _LIB_PATH)
+    """Compile ``liboracle.so`` (single-threaded C) and ``liboracle_omp.so`` next to this file with gcc."""
+    for path, extra in _FLAVOURS.items():
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["gcc", *_BASE_FLAGS, *extra, "-o", tmp, _SRC])
+            os.replace(tmp, path)
     return _LIB_PATH
 
 
+def build_sanitized(out_dir: str) -> str:
+    """The plain oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (host code only), for running the pins under the sanitizers."""
+    path = os.path.join(out_dir, "liboracle_san.so")
+    subprocess.check_call(["gcc", "-O1", "-g", "-std=gnu11", "-fPIC", "-shared", "-Wall",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+                           "-o", path, _SRC])
+    return path
+
+
 _lib = None
+_libs = {}
 _i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
 _u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
 
 
-def _load():
+def _load(omp: bool = False):
     global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+    path = _OMP_PATH if omp else os.environ.get("ORACLE_LIB", _LIB_PATH)
+    if path not in _libs:
+        if not os.path.exists(path):
             build(force=False)
-        lib = ctypes.CDLL(_LIB_PATH)
+        lib = ctypes.CDLL(path)
         i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
         lib.oracle_fixpoint.argtypes = [i32, i64, _i32p, _i32p, _u8p, i32, _i32p, ctypes.POINTER(i64)]
         lib.oracle_fixpoint.restype = ctypes.c_int
@@ -81,8 +99,17 @@ def _load():
         lib.oracle_lasso.restype = ctypes.c_int
         lib.oracle_trim.argtypes = [i32, i64, _i32p, _i32p, _u8p, _u8p, _u8p]
         lib.oracle_trim.restype = i64
-        _lib = lib
-    return _lib
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = ctypes.c_int
+        _libs[path] = lib
+        if not omp:
+            _lib = lib
+    return _libs[path]
+
+
+def threads(omp: bool = False) -> int:
+    """Host threads the jacobi route uses in the plain (1) or OpenMP build."""
+    return int(_load(omp).oracle_threads())
 
 
 def _arrays(g, acc=None):
@@ -138,8 +165,8 @@ class Detect:
 
 
 def map_detect(g, acc=None, mode: str = "desc", max_iterations: int = 0, trace_cap: int | None = None,
-               maps_cap: int = 0) -> Detect:
-    """Run the MAP outer loop on the oracle."""
+               maps_cap: int = 0, omp: bool = False) -> Detect:
+    """Run the MAP outer loop on the oracle (``omp``: the OpenMP build, same results)."""
     src, dst, a = _arrays(g, acc)
     n = g.n
     if trace_cap is None:
@@ -149,7 +176,7 @@ def map_detect(g, acc=None, mode: str = "desc", max_iterations: int = 0, trace_c
     acc_out = np.zeros(n, np.uint8)
     res = np.zeros(4, np.int32)
     sweeps = ctypes.c_int64(0)
-    rc = _load().oracle_map_detect(n, len(src), src, dst, a, MODES[mode], max_iterations, res,
+    rc = _load(omp).oracle_map_detect(n, len(src), src, dst, a, MODES[mode], max_iterations, res,
                                    ctypes.byref(sweeps), trace.ctypes.data, trace_cap,
                                    maps.ctypes.data if maps_cap > 0 else None, maps_cap,
                                    acc_out.ctypes.data)

@@ -50,6 +50,11 @@
  * self-loop) and the nested depth-first search of Courcoubetis, Vardi,
  * Wolper and Yannakakis.
  *
+ * Build flavours (same source, same arithmetic): the plain single-threaded
+ * build every test uses; with -fopenmp -DORACLE_OPENMP the edge loop of a
+ * jacobi pass is shared among the host's threads (used only to time the
+ * jacobi route on all host cores); and sanitizer builds for the CPU tests.
+ *
  * All ids are int32, 1..n; edges are (src[i] -> dst[i]); acc[i] flags id i+1.
  * Per-iteration digest: sum over v of mix64((v << 32) | map(v)) mod 2^64, with
  * mix64 the SplitMix64 finalizer (Steele, Lea & Flood, OOPSLA 2014).
@@ -57,6 +62,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef ORACLE_OPENMP
+#include <omp.h>
+#endif
 
 #define OR_OK 0
 #define OR_EINVAL -1
@@ -108,6 +116,31 @@ static int32_t sent(int32_t w, const int32_t *val, const uint8_t *acc) {
     return x;
 }
 
+#ifdef ORACLE_OPENMP
+/* next[v] = max(next[v], x), for edges of one source handled by different
+ * threads in the same pass. */
+static void raise_to(int32_t *p, int32_t x) {
+    int32_t cur = __atomic_load_n(p, __ATOMIC_RELAXED);
+    while (x > cur && !__atomic_compare_exchange_n(p, &cur, x, 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
+    }
+}
+#endif
+
+/* Threads the jacobi route uses (1 in the plain build). */
+int oracle_threads(void) {
+#ifdef ORACLE_OPENMP
+    int t = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        t = omp_get_num_threads();
+    }
+    return t;
+#else
+    return 1;
+#endif
+}
+
 /* jacobi: m_{t+1}(v) = max(m_t(v), max over edges v->w of sent_t(w)), from
  * m_0 = 0, until m_{t+1} == m_t.  *sweeps counts every pass made, including
  * the final pass that changes nothing. */
@@ -119,10 +152,15 @@ static int fix_jacobi(int32_t n, int64_t m, const int32_t *src, const int32_t *d
     int64_t t = 0;
     for (;;) {
         memcpy(next, map, (size_t)n * sizeof(int32_t));
+#ifdef ORACLE_OPENMP
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < m; ++i) raise_to(&next[src[i] - 1], sent(dst[i], map, acc));
+#else
         for (int64_t i = 0; i < m; ++i) {
             int32_t x = sent(dst[i], map, acc);
             if (x > next[src[i] - 1]) next[src[i] - 1] = x;
         }
+#endif
         t++;
         if (memcmp(next, map, (size_t)n * sizeof(int32_t)) == 0) break;
         memcpy(map, next, (size_t)n * sizeof(int32_t));

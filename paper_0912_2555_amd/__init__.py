@@ -18,7 +18,7 @@ Convenience wrappers (``Csr``, ``build_csr``, ``propagate``, ``detect``, ``lasso
 allocate the tensors, call the raw entry points and synchronize when results
 are read back.
 
-The library must be built (``python -m paper_0912_2555_amd.build``); importing
+The library must be built (``python paper_0912_2555_amd/build.py``); importing
 this package raises if ``libmapcheck.so`` is missing -- there is no fallback.
 """
 from __future__ import annotations
@@ -57,7 +57,7 @@ EXPORTS = ("map_workspace_bytes", "map_build_csr", "map_propagate", "map_detect"
            "map_trim", "map_strerror")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_0912_2555_amd.build` "
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_0912_2555_amd/build.py` "
                       "(there is no fallback implementation)")
 
 _lib = ctypes.CDLL(LIB_PATH)

@@ -1,6 +1,6 @@
 """Compile the HIP library ``libmapcheck.so`` in-tree for gfx950.
 
-Usage: ``python -m paper_0912_2555_amd.build``.  hipcc cross-compiles without a
+Usage: ``python paper_0912_2555_amd/build.py``.  hipcc cross-compiles without a
 GPU present.
 """
 from __future__ import annotations

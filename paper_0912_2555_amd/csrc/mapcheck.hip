@@ -69,15 +69,20 @@ constexpr int kMaxGang = 256;     // upper bound on the blocks that share one gr
 // Bound on one barrier wait, in ticks of the 100 MHz device wall clock (10 s):
 // far beyond any legitimate phase, so a broken launch exits instead of hanging.
 constexpr uint64_t kWaitTicks = 1000000000ull;
+// Bound on the asynchronous sweeping of one fixpoint computation (60 s of
+// device wall clock): a sweep loop that has not settled by then (a livelock)
+// ends the launch with MAP_EDEVICE instead of running on.
+constexpr uint64_t kIterTicks = 6000000000ull;
 
 // ------------------------------------------------------------------ ctrl --
 
 struct alignas(128) Stripe {
   unsigned long long digest;
+  unsigned long long sweeps;  // sweeps of the blocks of this stripe in the iteration
   uint32_t count;
   int32_t witness;
   uint32_t nonzero;
-  uint32_t pad[27];
+  uint32_t pad[25];
 };
 
 struct alignas(128) Line64 {
@@ -116,11 +121,30 @@ struct alignas(256) CtrlT {
 using Ctrl = CtrlT<kMaxBlocks>;
 using GangCtrl = CtrlT<kMaxGang>;
 constexpr size_t kCtrlBytes = 32768;
-static_assert(sizeof(Ctrl) <= kCtrlBytes, "ctrl block too large");
+// The last line of a single graph's control region holds the tag epoch, which
+// outlives the call (the per-call clear stops before it): the first iteration
+// tag of a call follows the last one of the previous call on the workspace.
+constexpr size_t kEpochOff = kCtrlBytes - 256;
+static_assert(sizeof(Ctrl) <= kEpochOff, "ctrl block too large");
 constexpr size_t kGangCtrlBytes = sizeof(GangCtrl);
 // Arrays of control blocks are indexed with GangCtrl pointers and cleared in
 // kGangCtrlBytes units: the two strides must agree.
 static_assert(kGangCtrlBytes % 256 == 0, "control blocks are 256-byte multiples");
+
+// Completes this wave's global writes before a workgroup barrier after which
+// the workgroup's leader publishes them to other workgroups (an agent-scope
+// release, then an atomic).  On gfx950 a workgroup-scope release waits only
+// for LDS operations (the waves of a workgroup share one CU's L1), and the
+// leader's agent-scope release -- an L2 write-back (`buffer_wbl2 sc1`) and a
+// wait on the leader's own wave's memory operations -- is documented to order
+// only that wave's operations.  Waiting here for every vector memory operation
+// of every wave (`s_waitcnt vmcnt(0)`: each store acknowledged by L2) puts all
+// of them in L2 before the barrier, so the leader's write-back that follows the
+// barrier covers them.
+__device__ __forceinline__ void wave_writes_done() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // gfx9 encoding of vmcnt(0), expcnt and lgkmcnt left at their maxima
+}
 
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -177,11 +201,11 @@ struct Grid {
 // Grid-wide barrier with a summed 32-bit payload.  Every thread must call it.
 // Returns false if the wait exceeded its bound (the kernel must then exit).
 //
-// Ordering: each block's leader issues one agent-scope release fence before
-// its arrival (cumulative over the block's waves through the workgroup
-// barrier); the last arrival of a group and the last group leader acquire
-// before forwarding; waiters poll with relaxed loads (no cache invalidation
-// per poll) and acquire once when the generation moves.
+// Ordering: every wave completes its global writes (wave_writes_done) before
+// the workgroup barrier; the block's leader then issues one agent-scope release
+// fence before its arrival; the last arrival of a group and the last group
+// leader acquire before forwarding; waiters poll with relaxed loads (no cache
+// invalidation per poll) and acquire once when the generation moves.
 template <typename C>
 __device__ bool grid_sync(Grid<C>& g, uint32_t payload, uint32_t* total) {
   __shared__ uint32_t s_total;
@@ -192,6 +216,7 @@ __device__ bool grid_sync(Grid<C>& g, uint32_t payload, uint32_t* total) {
     if (threadIdx.x < kStripes) {
       Stripe& s = g.c->sets[(g.gen + 2) % kSets][threadIdx.x];
       __hip_atomic_store(&s.digest, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&s.sweeps, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       st_agent(&s.count, 0u);
       __hip_atomic_store(&s.witness, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       st_agent(&s.nonzero, 0u);
@@ -201,7 +226,7 @@ __device__ bool grid_sync(Grid<C>& g, uint32_t payload, uint32_t* total) {
     if (total) *total = payload;
     return true;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  wave_writes_done();
   __syncthreads();
   if (threadIdx.x == 0) {
     C* c = g.c;
@@ -243,6 +268,7 @@ __device__ bool grid_sync(Grid<C>& g, uint32_t payload, uint32_t* total) {
   if (g.rank == 0 && threadIdx.x < kStripes) {
     Stripe& s = g.c->sets[(g.gen + 2) % kSets][threadIdx.x];
     __hip_atomic_store(&s.digest, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&s.sweeps, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     st_agent(&s.count, 0u);
     __hip_atomic_store(&s.witness, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     st_agent(&s.nonzero, 0u);
@@ -274,7 +300,9 @@ struct LoopArgs {
   int32_t force_stream;  // 1: never stage the CSR in LDS
   int32_t sync_sweeps;   // 1: a grid barrier after every sweep instead of the asynchronous fixpoint
   uint32_t val_mask;     // bits of a packed word holding the map value
-  uint32_t par_bit;      // bit holding the iteration parity (0: untagged, n >= 2^30)
+  uint32_t tag_mask;     // bits holding the iteration tag (0: untagged, n >= 2^30)
+  uint32_t tag_shift;    // lowest bit of the tag
+  uint32_t* epoch;       // single graph: the workspace's tag epoch word (else null)
   int32_t push;          // 1: frontier sweeps over the transposed CSR (barrier per round)
   int32_t early;         // 1: stop once a value equals its own row's id (MAP_FLAG_EARLY)
   const int32_t* rrow_ptr;  // push: transposed CSR (row w = predecessors of w)
@@ -339,14 +367,43 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Layout of a packed value word for ids 1..n: the value takes the bit length
+// of n, the accepting flag bit 31, and the iteration tag the bits between
+// (none when n >= 2^30, one bit -- the iteration parity -- when n >= 2^29).
+__host__ __device__ inline void word_layout(int32_t n, uint32_t* vmask, uint32_t* tmask, uint32_t* tshift) {
+  int vbits = 0;
+  while (vbits < 31 && ((uint32_t)n >> vbits) != 0u) ++vbits;
+  if (vbits >= 31) {
+    *vmask = kValMask;
+    *tmask = 0u;
+    *tshift = 31u;
+    return;
+  }
+  *vmask = (1u << vbits) - 1u;
+  *tmask = kValMask & ~*vmask;
+  *tshift = (uint32_t)vbits;
+}
+
+// Tag of the words written in iteration k (k >= 1) of a call whose epoch is
+// `base`.  With two or more tag bits the tags run through 1 .. 2^T - 1 (tag 0,
+// the launch-start clear, is never current), consecutive iterations differ,
+// and a call starts right after the tags its predecessor on the workspace
+// used; with one bit the tag is the parity of k.
+__device__ __forceinline__ uint32_t iter_tag(uint32_t tmask, uint32_t tshift, uint32_t base, int32_t k) {
+  if (tmask == 0u) return 0u;
+  const uint32_t span = tmask >> tshift;
+  if (span == 1u) return (k & 1) ? tmask : 0u;
+  return (1u + (base + (uint32_t)k - 1u) % span) << tshift;
+}
+
 // Value that successor w (0-based) sends along an edge: its map value, or its
-// own id if it is accepting and larger.  A word tagged with the other
-// iteration parity has not been reset in this iteration yet and sends 0, a
-// valid lower bound (its owner's reset sweep then counts as a change, so the
-// reader sweeps again once the true value is there).
-__device__ __forceinline__ uint32_t sent_word(uint32_t x, int32_t w, uint32_t cur, uint32_t vmask, uint32_t pbit) {
+// own id if it is accepting and larger.  A word tagged with another iteration
+// has not been reset in this iteration yet and sends 0, a valid lower bound
+// (its owner's reset sweep then counts as a change, so the reader sweeps again
+// once the true value is there).
+__device__ __forceinline__ uint32_t sent_word(uint32_t x, int32_t w, uint32_t cur, uint32_t vmask, uint32_t tmask) {
   const uint32_t id = (uint32_t)w + 1u;
-  if ((x & pbit) != cur) return 0u;
+  if ((x & tmask) != cur) return 0u;
   const uint32_t m = x & vmask;
   return (x & kAccBit) ? (m > id ? m : id) : m;
 }
@@ -368,7 +425,7 @@ __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int64_t r0
   g_ci32* colp = (g_ci32*)a.col;
   g_u32* pv = (g_u32*)a.pv;
   g_cu8* gacc = (g_cu8*)acc;
-  const uint32_t n = (uint32_t)a.n, vmask = a.val_mask, pbit = a.par_bit;
+  const uint32_t n = (uint32_t)a.n, vmask = a.val_mask, tmask = a.tag_mask;
   for (int i = lane; i <= nr; i += kWave) L.rp[i] = __builtin_nontemporal_load(row_ptr + r0 + i);
   wave_lds_sync();
   const int32_t e0 = L.rp[0], e1 = L.rp[nr];
@@ -394,7 +451,7 @@ __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int64_t r0
     for (int u = 0; u < kEdgesPerLane; ++u) {
       int i = lane + u * kWave;
       uint32_t x = 0;
-      if ((uint32_t)w[u] < n) x = kFirst ? sent_first(acc, w[u]) : sent_word(pv[w[u]], w[u], cur, vmask, pbit);
+      if ((uint32_t)w[u] < n) x = kFirst ? sent_first(acc, w[u]) : sent_word(pv[w[u]], w[u], cur, vmask, tmask);
       if (i < cnt) L.val[i] = x;
     }
     wave_lds_sync();
@@ -437,7 +494,7 @@ __device__ __forceinline__ void gather_range(const uint8_t* acc, int32_t e0, int
                                              const LoopArgs& a, int lane, uint32_t cur) {
   ResLds& R = g_lds.res;
   g_u32* pv = (g_u32*)a.pv;
-  const uint32_t n = (uint32_t)a.n, vmask = a.val_mask, pbit = a.par_bit;
+  const uint32_t n = (uint32_t)a.n, vmask = a.val_mask, tmask = a.tag_mask;
   for (int32_t k0 = e0; k0 < e1; k0 += kWave * kGatherBatch) {
     uint32_t e[kGatherBatch];
 #pragma unroll
@@ -452,7 +509,7 @@ __device__ __forceinline__ void gather_range(const uint8_t* acc, int32_t e0, int
       const uint32_t w = e[u] >> 8;
       if (e[u] != 0xffffffffu && w < n) {
         if (kSrc == 0) x[u] = sent_first(acc, (int32_t)w);
-        else x[u] = sent_word(pv[w], (int32_t)w, cur, vmask, pbit);
+        else x[u] = sent_word(pv[w], (int32_t)w, cur, vmask, tmask);
       }
     }
 #pragma unroll
@@ -477,7 +534,7 @@ __device__ __forceinline__ int row_step(const WaveRows& W, int jj) {
 __device__ uint32_t local_pass(const LoopArgs& a, const WaveRows& W, int lane, uint32_t cur) {
   ResLds& R = g_lds.res;
   g_u32* pv = (g_u32*)a.pv;
-  const uint32_t vmask = a.val_mask, pbit = a.par_bit, base = (uint32_t)W.rb0;
+  const uint32_t vmask = a.val_mask, tmask = a.tag_mask, base = (uint32_t)W.rb0;
   const int32_t nrow = (int32_t)(W.r1 - W.r0), r0 = (int32_t)(W.r0 - W.rb0);
   uint32_t changed = 0;
 #pragma unroll
@@ -489,7 +546,7 @@ __device__ uint32_t local_pass(const LoopArgs& a, const WaveRows& W, int lane, u
       uint32_t b = 0;
       for (int32_t k = R.lrow[li]; k < k1; ++k) {
         const uint32_t t = R.e[k];
-        b = max(b, sent_word(R.pv[t], (int32_t)(base + t), cur, vmask, pbit));
+        b = max(b, sent_word(R.pv[t], (int32_t)(base + t), cur, vmask, tmask));
       }
       const uint32_t old = R.pv[li];
       if (b > (old & vmask)) {
@@ -707,6 +764,10 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = threadIdx.x / kWave;
   if (kEarly && threadIdx.x == 0) g_early = 0;  // ordered before its first use by the set-up's barriers
+  // Tag epoch of this call: left by the previous call on the workspace (an
+  // earlier kernel); block 0 writes the next one only after the first grid
+  // barrier, which every block reaches after this read.
+  const uint32_t tbase = a.epoch ? *a.epoch : 0u;
 
   // Row ranges of this block and wave.
   const int64_t rows_per_block = ((int64_t)a.n + nb - 1) / nb;
@@ -829,9 +890,12 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     uint32_t t = lane < kStripes ? ld_agent(&c->sets[set][lane].count) : 0u;
     return wave_sum_u32(t);
   };
-  // Any wave of the block changed a row: one flag per block for the barrier.
+  // Any wave of the block changed a row: one flag per block.  Each wave first
+  // completes its writes, so that the leader's release after this barrier
+  // (change report, or grid barrier) covers every wave's new values.
   auto block_any = [&](uint32_t ch) {
     if (lane == 0) s_red[wib] = ch;
+    wave_writes_done();
     __syncthreads();
     uint32_t any = 0;
     for (int i = 0; i < kWavesPerBlock; ++i) any |= s_red[i];
@@ -842,7 +906,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
   uint32_t count_prev = 0;  // |A_k| of the last completed iteration
   uint32_t rtag = 0;        // push: frontier round, the same in every block
   int32_t k = 0;
-  int64_t total_sweeps = 0;
+  int64_t total_sweeps = 0;  // sweeps summed over the blocks (every block the same in barrier mode)
   int32_t status = MAP_OK, found = 0, witness = 0;
   int32_t left = 0;
   bool acc_from_pv = false;  // acc_out comes from the accepting bits of the packed values
@@ -875,9 +939,9 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
 
   for (;;) {
     k++;
-    // Iteration tag: values written in iteration k carry the parity of k; a
-    // reader that finds the other parity takes the reset value instead.
-    const uint32_t cur = (k & 1) ? a.par_bit : 0u;
+    // Iteration tag: values written in iteration k carry the tag of k; a
+    // reader that finds another tag takes the reset value instead.
+    const uint32_t cur = iter_tag(a.tag_mask, a.tag_shift, tbase, k);
     uint32_t nacc = 0;       // accepting rows of this block in A_k (reset sweep)
     uint32_t cnt_k = 0;      // |A_k|
     int64_t s = 0;           // sweeps of this block in iteration k
@@ -896,10 +960,9 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     //    fixpoint: block 0 then publishes done = k.
     const uint32_t tag = (uint32_t)k;
     uint32_t d_seen = 0xffffffffu;  // async: counter value of this block's last quiet sweep (wave 0)
-    // |A_k| <= |A_{k-1}| (detect); any accepting set has at most n vertices (propagate).
-    const int64_t acnt = a.propagate ? (int64_t)a.n : (int64_t)count_prev;
-    const int64_t sweep_cap =
-        acnt + 1 > (INT64_MAX / 4) / (int64_t)a.n ? INT64_MAX : 2 * (int64_t)a.n * (acnt + 1) + 16;
+    // Async: start of this fixpoint computation on the device wall clock
+    // (wave 0), against which kIterTicks bounds the sweeping.
+    const uint64_t t_iter = wall_clock64();
     // After a sweep: the barrier (sync) or the change / quiet report (async).
     // Returns false when the launch must stop.
     auto report = [&](uint32_t any, uint32_t d0) -> bool {
@@ -924,14 +987,6 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
         }
       }
       if (wib == 0) d_seen = any ? 0xffffffffu : d0;
-      // Safety net, unreachable for a monotone fixpoint: every change raises a
-      // row to one of at most |A_k| + 1 values, so the blocks make at most
-      // n (|A_k| + 1) changing sweeps together, and a block sweeps after its
-      // own changes and after the counter moves, at most twice that plus one.
-      if (s > sweep_cap) {
-        if (threadIdx.x == 0) st_agent((uint32_t*)&c->abort, 1u);
-        return false;
-      }
       return true;
     };
     // MAP_FLAG_EARLY: after a sweep, the block's rows whose value is their
@@ -1001,7 +1056,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
           uint32_t x = 0;
           if (i < (int64_t)S) {
             const int32_t w = F[i];
-            x = sent_word(pvg[w], w, cur, a.val_mask, a.par_bit);
+            x = sent_word(pvg[w], w, cur, a.val_mask, a.tag_mask);
             if (x) {
               k = a.rrow_ptr[w];
               k1 = a.rrow_ptr[w + 1];
@@ -1059,6 +1114,9 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
           for (;;) {
             if (ld_agent(&c->done) == tag) { cmd = 1; break; }
             if (kEarly && ld_agent(&c->early)) { cmd = 1; break; }
+            // Sweeping that has not settled within kIterTicks ends the launch,
+            // however often the counter moves.
+            if (wall_clock64() - t_iter > kIterTicks) { cmd = 2; break; }
             const uint32_t d = ld_agent(&c->dirty);
             if (d != d_seen) { cmd = 0; d0 = d; break; }
             if (b == 0) {
@@ -1098,8 +1156,19 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     // Asynchronous mode: |A_k| is reduced together with the detect pass (same
     // barrier epoch).
     if (!sync && !a.propagate) block_add_count(nacc, g.gen % kSets);
-    if (status != MAP_OK) { total_sweeps += s; left = (int32_t)count_prev; acc_from_pv = !a.propagate; break; }
-    if (a.propagate) { total_sweeps += s; break; }
+    if (status != MAP_OK) { total_sweeps += s * nb; left = (int32_t)count_prev; acc_from_pv = !a.propagate; break; }
+    if (a.propagate) {
+      // The blocks' sweep counts, summed at one more barrier.
+      if (threadIdx.x == 0 && s)
+        __hip_atomic_fetch_add(&c->sets[g.gen % kSets][b % kStripes].sweeps, (unsigned long long)s,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ok = grid_sync(g, 0, nullptr);
+      if (!ok) goto aborted;
+      unsigned long long sw = lane < kStripes ? __hip_atomic_load(&c->sets[(g.gen - 1) % kSets][lane].sweeps,
+                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+      total_sweeps += (int64_t)wave_sum_u64(sw);
+      break;
+    }
 
     // Detect and strip: witness = max v with map(v) == v; every nonzero map
     // value loses its accepting flag (the flags of this iteration stay in the
@@ -1131,6 +1200,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
         Stripe& st = c->sets[g.gen % kSets][b % kStripes];
         if (bw) __hip_atomic_fetch_max(&st.witness, bw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (bd) __hip_atomic_fetch_add(&st.digest, bd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (s) __hip_atomic_fetch_add(&st.sweeps, (unsigned long long)s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (bn) __hip_atomic_fetch_add(&st.nonzero, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       __syncthreads();
@@ -1139,17 +1209,19 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
       const int set = (g.gen - 1) % kSets;
       // Lane i of every wave reads stripe i; the wave combines them.
       int32_t w2 = 0;
-      unsigned long long d2 = 0;
+      unsigned long long d2 = 0, sw2 = 0;
       uint32_t nz2 = 0, cnt2 = 0;
       if (lane < kStripes) {
         Stripe& st = c->sets[set][lane];
         w2 = __hip_atomic_load(&st.witness, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         d2 = __hip_atomic_load(&st.digest, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sw2 = __hip_atomic_load(&st.sweeps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         nz2 = ld_agent(&st.nonzero);
         cnt2 = ld_agent(&st.count);
       }
       w2 = wave_max_i32(w2);
       d2 = wave_sum_u64(d2);
+      sw2 = wave_sum_u64(sw2);
       nz2 = wave_sum_u32(nz2);
       cnt2 = wave_sum_u32(cnt2);
       if (!sync) cnt_k = cnt2;
@@ -1164,13 +1236,16 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
         left = 0;
         break;
       }
-      total_sweeps += s;
+      total_sweeps += (int64_t)sw2;
+      // Whole-graph sweeps of iteration k: the blocks' sweeps over their
+      // count, rounded (in barrier mode every block's count).
+      const int64_t sweeps_k = ((int64_t)sw2 + nb / 2) / nb;
       if (leader && a.trace) {
         if (k >= 2 && k - 1 <= a.trace_cap) a.trace[(int64_t)(k - 2) * 3 + 0] = (uint64_t)(count_prev - cnt_k);
         if (k <= a.trace_cap) {
           uint64_t* row = a.trace + (int64_t)(k - 1) * 3;
           row[0] = 0;
-          row[1] = (uint64_t)s;
+          row[1] = (uint64_t)sweeps_k;
           row[2] = want_digest ? d2 : 0ull;
         }
       }
@@ -1210,11 +1285,14 @@ done:
     });
   }
   if (b == 0 && threadIdx.x == 0) {
+    // Words now carry the tags of iterations k and, where a reset was cut
+    // short, k - 1: the next call's first tag is past both.
+    if (a.epoch) *a.epoch = tbase + (uint32_t)k + 1u;
     a.result->found = found;
     a.result->witness = witness;
     a.result->iterations = a.propagate ? 0 : k;
     a.result->status = status;
-    a.result->sweeps = total_sweeps;
+    a.result->sweeps = (total_sweeps + nb / 2) / nb;
     a.result->accepting_left = a.propagate ? 0 : left;
     a.result->reserved = 0;
   }
@@ -1270,7 +1348,7 @@ __device__ __noinline__ void map_body_gang_sync_early(const LoopArgs& a, GangCtr
 }
 // One graph solved by a gang, in the fixpoint control and mode its arguments ask for.
 __device__ __forceinline__ void map_body_gang(const LoopArgs& a, GangCtrl* c, int nb, int rank) {
-  const bool async = nb > 1 && !a.sync_sweeps && a.par_bit;
+  const bool async = nb > 1 && !a.sync_sweeps && a.tag_mask;
   if (a.early) {
     if (async) map_body_gang_async_early(a, c, nb, rank);
     else map_body_gang_sync_early(a, c, nb, rank);
@@ -1754,8 +1832,8 @@ __device__ LoopArgs gang_args(int32_t n, const int32_t* row_ptr, const int32_t* 
   a.digest = 0;
   a.force_stream = (flags & MAP_FLAG_STREAM) ? 1 : 0;
   a.sync_sweeps = (flags & MAP_FLAG_SYNC_SWEEPS) ? 1 : 0;
-  a.val_mask = n < (1 << 30) ? 0x3fffffffu : kValMask;
-  a.par_bit = n < (1 << 30) ? 0x40000000u : 0u;
+  word_layout(n, &a.val_mask, &a.tag_mask, &a.tag_shift);
+  a.epoch = nullptr;
   a.push = 0;
   a.early = (flags & MAP_FLAG_EARLY) ? 1 : 0;
   a.rrow_ptr = nullptr;
@@ -2050,7 +2128,7 @@ __device__ __noinline__ void engine_job(const EngineArgs& ea, int slot, int rank
       pm[i] = 0u;
     }
     if (threadIdx.x < 8) reinterpret_cast<uint32_t*>(res)[threadIdx.x] = 0u;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    wave_writes_done();
     __syncthreads();
     if (threadIdx.x == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -2087,7 +2165,7 @@ __device__ __noinline__ void engine_job(const EngineArgs& ea, int slot, int rank
   }
   // Leave the job: release this block's writes, then report (ranks > 0) or
   // wait for the others and publish the result (rank 0).
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  wave_writes_done();
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -2478,10 +2556,10 @@ int launch_loop(LoopArgs& a, hipStream_t stream) {
   if (grid >= kMaxGroups) grid -= grid % kMaxGroups;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(fill_u32, dim3(8), dim3(256), 0, stream, reinterpret_cast<uint32_t*>(a.ctrl),
-                     (int64_t)(kCtrlBytes / 4), 0u);
+                     (int64_t)(kEpochOff / 4), 0u);
   if (hipGetLastError() != hipSuccess) return MAP_EDEVICE;
   void* args[] = {&a};
-  const bool async = grid > 1 && !a.sync_sweeps && a.par_bit != 0;
+  const bool async = grid > 1 && !a.sync_sweeps && a.tag_mask != 0;
   const void* kernel =
       a.early ? (async ? reinterpret_cast<const void*>(map_loop_kernel<true, true>)
                        : reinterpret_cast<const void*>(map_loop_kernel<false, true>))
@@ -2680,8 +2758,8 @@ static int loop_common(int32_t n, const int32_t* row_ptr, const int32_t* col, co
   a.accw = reinterpret_cast<uint8_t*>(w + L.accw);
   a.ctrl = reinterpret_cast<Ctrl*>(w + L.ctrl);
   a.result = result;
-  a.val_mask = n < (1 << 30) ? 0x3fffffffu : kValMask;
-  a.par_bit = n < (1 << 30) ? 0x40000000u : 0u;
+  word_layout(n, &a.val_mask, &a.tag_mask, &a.tag_shift);
+  a.epoch = reinterpret_cast<uint32_t*>(w + L.ctrl + kEpochOff);
   return MAP_OK;
 }
 
@@ -2773,7 +2851,7 @@ int map_lasso(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t wit
   a.ctrl = reinterpret_cast<Ctrl*>(w + L.ctrl);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(fill_u32, dim3(8), dim3(256), 0, st, reinterpret_cast<uint32_t*>(a.ctrl),
-                     (int64_t)(kCtrlBytes / 4), 0u);
+                     (int64_t)(kEpochOff / 4), 0u);
   if (hipGetLastError() != hipSuccess) return MAP_EDEVICE;
   void* args[] = {&a};
   if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(map_lasso_kernel), dim3((unsigned)grid), dim3(kBlock),
@@ -2812,7 +2890,7 @@ int map_trim(int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_
   a.ctrl = reinterpret_cast<Ctrl*>(w + L.ctrl);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(fill_u32, dim3(8), dim3(256), 0, st, reinterpret_cast<uint32_t*>(a.ctrl),
-                     (int64_t)(kCtrlBytes / 4), 0u);
+                     (int64_t)(kEpochOff / 4), 0u);
   if (hipGetLastError() != hipSuccess) return MAP_EDEVICE;
   void* args[] = {&a};
   if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(map_trim_kernel), dim3((unsigned)grid), dim3(kBlock),

@@ -40,7 +40,7 @@ def test_expected_values_agree_with_the_oracle():
 
 
 def test_c_example_runs():
-    assert os.path.exists(EXAMPLE), "the C example is not built (python -m paper_0912_2555_amd.build)"
+    assert os.path.exists(EXAMPLE), "the C example is not built (python paper_0912_2555_amd/build.py)"
     r = subprocess.run([EXAMPLE], capture_output=True, text=True, timeout=120)
     print(r.stdout, r.stderr, flush=True)
     assert r.returncode == 0

@@ -16,7 +16,7 @@ MAP_OK, MAP_EINVAL, MAP_ERANGE, MAP_ENOSPC = 0, -1, -2, -3
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        pytest.fail("libmapcheck.so is not built (python -m paper_0912_2555_amd.build)")
+        pytest.fail("libmapcheck.so is not built (python paper_0912_2555_amd/build.py)")
     lib = ctypes.CDLL(LIB)
     vp, i32, i64, u32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
     lib.map_workspace_bytes.argtypes = [i32, i64, u32]
