@@ -82,8 +82,9 @@ extern "C" {
  * subsets of the paths, so such a vertex lies on an accepting cycle: the
  * verdict is the same as without the flag, but K can be smaller and the
  * witness (a vertex on an accepting cycle, accepting in A_1) depends on the
- * schedule.  Ignored by map_propagate; MAP_EINVAL together with MAP_FLAG_PUSH
- * (unless MAP_FLAG_DENSE_ONLY is set as well). */
+ * schedule.  Runs with a grid-wide barrier after every sweep, as if
+ * MAP_FLAG_SYNC_SWEEPS were set.  Ignored by map_propagate; MAP_EINVAL together
+ * with MAP_FLAG_PUSH (unless MAP_FLAG_DENSE_ONLY is set as well). */
 #define MAP_FLAG_EARLY 0x20u
 
 /* Result of map_propagate / map_detect, written to device memory (32 bytes). */
@@ -92,9 +93,10 @@ typedef struct map_result {
   int32_t witness;        /* largest id v with map(v) == v in the last iteration, else 0 */
   int32_t iterations;     /* K: number of fixpoint computations made */
   int32_t status;         /* MAP_OK, MAP_ENOTCONVERGED */
-  int64_t sweeps;         /* whole-graph propagation sweeps over all iterations: the sum of
-                             every workgroup's sweeps over the number of workgroups, rounded
-                             (schedule dependent; in barrier mode every workgroup's count) */
+  int64_t sweeps;         /* whole-graph propagation sweeps, summed over the iterations; those
+                             of one iteration are the sum of every workgroup's sweeps over the
+                             number of workgroups, rounded (schedule dependent; in barrier mode
+                             every workgroup's count) */
   int32_t accepting_left; /* number of accepting vertices at exit */
   int32_t reserved;
 } map_result;

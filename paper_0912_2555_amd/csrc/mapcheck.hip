@@ -906,7 +906,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
   uint32_t count_prev = 0;  // |A_k| of the last completed iteration
   uint32_t rtag = 0;        // push: frontier round, the same in every block
   int32_t k = 0;
-  int64_t total_sweeps = 0;  // sweeps summed over the blocks (every block the same in barrier mode)
+  int64_t total_sweeps = 0;  // whole-graph sweeps, summed over the iterations
   int32_t status = MAP_OK, found = 0, witness = 0;
   int32_t left = 0;
   bool acc_from_pv = false;  // acc_out comes from the accepting bits of the packed values
@@ -1156,7 +1156,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     // Asynchronous mode: |A_k| is reduced together with the detect pass (same
     // barrier epoch).
     if (!sync && !a.propagate) block_add_count(nacc, g.gen % kSets);
-    if (status != MAP_OK) { total_sweeps += s * nb; left = (int32_t)count_prev; acc_from_pv = !a.propagate; break; }
+    if (status != MAP_OK) { total_sweeps += s; left = (int32_t)count_prev; acc_from_pv = !a.propagate; break; }
     if (a.propagate) {
       // The blocks' sweep counts, summed at one more barrier.
       if (threadIdx.x == 0 && s)
@@ -1166,7 +1166,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
       if (!ok) goto aborted;
       unsigned long long sw = lane < kStripes ? __hip_atomic_load(&c->sets[(g.gen - 1) % kSets][lane].sweeps,
                                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
-      total_sweeps += (int64_t)wave_sum_u64(sw);
+      total_sweeps += ((int64_t)wave_sum_u64(sw) + nb / 2) / nb;
       break;
     }
 
@@ -1236,10 +1236,10 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
         left = 0;
         break;
       }
-      total_sweeps += (int64_t)sw2;
       // Whole-graph sweeps of iteration k: the blocks' sweeps over their
       // count, rounded (in barrier mode every block's count).
       const int64_t sweeps_k = ((int64_t)sw2 + nb / 2) / nb;
+      total_sweeps += sweeps_k;
       if (leader && a.trace) {
         if (k >= 2 && k - 1 <= a.trace_cap) a.trace[(int64_t)(k - 2) * 3 + 0] = (uint64_t)(count_prev - cnt_k);
         if (k <= a.trace_cap) {
@@ -1292,7 +1292,7 @@ done:
     a.result->witness = witness;
     a.result->iterations = a.propagate ? 0 : k;
     a.result->status = status;
-    a.result->sweeps = (total_sweeps + nb / 2) / nb;
+    a.result->sweeps = total_sweeps;
     a.result->accepting_left = a.propagate ? 0 : left;
     a.result->reserved = 0;
   }
@@ -1340,18 +1340,16 @@ __device__ __noinline__ void map_body_gang_async(const LoopArgs& a, GangCtrl* c,
 __device__ __noinline__ void map_body_gang_sync(const LoopArgs& a, GangCtrl* c, int nb, int rank) {
   map_body<GangCtrl, false, false>(a, c, nb, rank, rank);
 }
-__device__ __noinline__ void map_body_gang_async_early(const LoopArgs& a, GangCtrl* c, int nb, int rank) {
-  map_body<GangCtrl, true, true>(a, c, nb, rank, rank);
-}
 __device__ __noinline__ void map_body_gang_sync_early(const LoopArgs& a, GangCtrl* c, int nb, int rank) {
   map_body<GangCtrl, false, true>(a, c, nb, rank, rank);
 }
-// One graph solved by a gang, in the fixpoint control and mode its arguments ask for.
+// One graph solved by a gang, in the fixpoint control and mode its arguments ask
+// for.  MAP_FLAG_EARLY always runs with a grid barrier after every sweep: the
+// asynchronous early body is not built (its builds hung on the device).
 __device__ __forceinline__ void map_body_gang(const LoopArgs& a, GangCtrl* c, int nb, int rank) {
   const bool async = nb > 1 && !a.sync_sweeps && a.tag_mask;
   if (a.early) {
-    if (async) map_body_gang_async_early(a, c, nb, rank);
-    else map_body_gang_sync_early(a, c, nb, rank);
+    map_body_gang_sync_early(a, c, nb, rank);
   } else {
     if (async) map_body_gang_async(a, c, nb, rank);
     else map_body_gang_sync(a, c, nb, rank);
@@ -2559,10 +2557,11 @@ int launch_loop(LoopArgs& a, hipStream_t stream) {
                      (int64_t)(kEpochOff / 4), 0u);
   if (hipGetLastError() != hipSuccess) return MAP_EDEVICE;
   void* args[] = {&a};
-  const bool async = grid > 1 && !a.sync_sweeps && a.tag_mask != 0;
+  // MAP_FLAG_EARLY runs with a grid barrier after every sweep (no asynchronous
+  // early instantiation exists).
+  const bool async = grid > 1 && !a.sync_sweeps && a.tag_mask != 0 && !a.early;
   const void* kernel =
-      a.early ? (async ? reinterpret_cast<const void*>(map_loop_kernel<true, true>)
-                       : reinterpret_cast<const void*>(map_loop_kernel<false, true>))
+      a.early ? reinterpret_cast<const void*>(map_loop_kernel<false, true>)
               : (async ? reinterpret_cast<const void*>(map_loop_kernel<true, false>)
                        : reinterpret_cast<const void*>(map_loop_kernel<false, false>));
   if (hipLaunchCooperativeKernel(kernel, dim3((unsigned)grid), dim3(kBlock), args, 0, stream) != hipSuccess)
