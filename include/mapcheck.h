@@ -171,6 +171,26 @@ int map_detect(int32_t n, const int32_t *row_ptr, const int32_t *col, const int3
                int32_t trace_cap, uint8_t *accepting_out, int32_t max_iterations, uint32_t flags, void *ws,
                size_t ws_bytes, void *stream);
 
+/* map_detect without a workspace and without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, results and
+ * errors as map_detect, except:
+ *   - scratch is a fixed array in the library's device memory (about 21 MB on
+ *     every device that calls this, held until the process ends) instead of a
+ *     workspace; n above MAP_NOALLOC_MAX_N is MAP_ERANGE;
+ *   - frontier sweeps are not available (no transposed CSR argument):
+ *     MAP_FLAG_PUSH without MAP_FLAG_DENSE_ONLY is MAP_EINVAL;
+ *   - every call on one device shares that device's array, which keeps the
+ *     last call's contents (each call starts from what it initialises): calls
+ *     that overlap on one device race, so the caller serializes them (one
+ *     stream, or synchronization between streams).
+ * The first call on a device looks up the array's device address
+ * (hipGetSymbolAddress); no call allocates or frees memory. */
+#define MAP_NOALLOC_MAX_N (1 << 22)
+int map_detect_noalloc(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint8_t *accepting0,
+                       map_result *result, uint64_t *trace, int32_t trace_cap, uint8_t *accepting_out,
+                       int32_t max_iterations, uint32_t flags, void *stream);
+
 /* Result of map_lasso (device memory, 32 bytes). */
 typedef struct map_lasso_result {
   int32_t status;        /* MAP_OK, MAP_ENOPATH, MAP_ENOSPC (path_cap too small), MAP_ERANGE_DEV, MAP_EDEVICE */

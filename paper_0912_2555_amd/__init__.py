@@ -50,11 +50,12 @@ MAP_FLAG_STREAM = 0x4
 MAP_FLAG_SYNC_SWEEPS = 0x8
 MAP_FLAG_PUSH = 0x10
 MAP_FLAG_EARLY = 0x20
+MAP_NOALLOC_MAX_N = 1 << 22
 
 EXPORTS = ("map_workspace_bytes", "map_build_csr", "map_propagate", "map_detect", "map_batch_workspace_bytes",
            "map_detect_batch", "map_job_scratch_bytes", "map_engine_create", "map_engine_workgroups",
            "map_engine_submit", "map_engine_poll", "map_engine_stop", "map_engine_destroy", "map_lasso",
-           "map_trim", "map_strerror")
+           "map_trim", "map_strerror", "map_detect_noalloc")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python paper_0912_2555_amd/build.py` "
@@ -70,6 +71,8 @@ _lib.map_propagate.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u32, _v
 _lib.map_propagate.restype = ctypes.c_int
 _lib.map_detect.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _i32, _u32, _vp, _sz, _vp]
 _lib.map_detect.restype = ctypes.c_int
+_lib.map_detect_noalloc.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _i32, _u32, _vp]
+_lib.map_detect_noalloc.restype = ctypes.c_int
 _lib.map_lasso.argtypes = [_i32, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _sz, _vp]
 _lib.map_lasso.restype = ctypes.c_int
 _lib.map_trim.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
@@ -171,6 +174,13 @@ def map_detect(n, row_ptr, col, rrow_ptr, rcol, accepting0, result, trace, accep
     return _lib.map_detect(n, _ptr(row_ptr), _ptr(col), _ptr(rrow_ptr), _ptr(rcol), _ptr(accepting0),
                            _ptr(result), _ptr(trace), cap, _ptr(accepting_out), max_iterations, flags, _ptr(ws),
                            0 if ws is None else ws.numel() * ws.element_size(), _stream(stream))
+
+
+def map_detect_noalloc(n, row_ptr, col, accepting0, result, trace, accepting_out, max_iterations, flags,
+                       stream=None) -> int:
+    cap = 0 if trace is None else int(trace.shape[0])
+    return _lib.map_detect_noalloc(n, _ptr(row_ptr), _ptr(col), _ptr(accepting0), _ptr(result), _ptr(trace), cap,
+                                   _ptr(accepting_out), max_iterations, flags, _stream(stream))
 
 
 def map_lasso(n, row_ptr, col, witness, init, path, result, ws, stream=None) -> int:

@@ -2696,6 +2696,33 @@ int frontier_grid(const void* kernel, int32_t n, int64_t* grid_out) {
 
 constexpr int32_t kEngineRing = 1 << 17;  // ticket ring entries (1 MiB of host memory)
 
+// Fixed device scratch of map_detect_noalloc, for callers that cannot allocate:
+// the control block, packed values and working accepting flags of one graph of
+// at most MAP_NOALLOC_MAX_N vertices, laid out as in a map_detect workspace.
+// Each device that runs the library holds its own copy until the process ends.
+constexpr size_t kNoAllocBytes = kCtrlBytes + (size_t)MAP_NOALLOC_MAX_N * 4 + (size_t)MAP_NOALLOC_MAX_N;
+static_assert(kCtrlBytes % 256 == 0 && ((size_t)MAP_NOALLOC_MAX_N * 4) % 256 == 0,
+              "no-alloc scratch regions are 256-byte aligned");
+static __device__ __align__(256) char noalloc_scratch[kNoAllocBytes];
+
+// Device address of noalloc_scratch on each device, taken once per device with
+// that device current (the array's name in host code is only a stand-in).
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[64];
+
+int noalloc_scratch_ptr(char** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return MAP_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)) != hipSuccess || !p) return MAP_EDEVICE;
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = static_cast<char*>(g_noalloc_ptr[dev]);
+  return MAP_OK;
+}
+
 }  // namespace
 
 // Host state of a serving engine (one per map_engine_create).
@@ -2740,13 +2767,10 @@ int map_build_csr(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, 
   return rc;
 }
 
-static int loop_common(int32_t n, const int32_t* row_ptr, const int32_t* col, const uint8_t* acc, map_result* result,
-                       void* ws, size_t ws_bytes, LoopArgs& a) {
-  if (n < 1 || n > 0x7ffffffe) return MAP_ERANGE;
-  if (!row_ptr || !col || !acc || !result || !ws) return MAP_EINVAL;
-  const Layout L = layout(n);
-  if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return MAP_ENOSPC;
-  char* w = static_cast<char*>(ws);
+// Loop arguments over scratch at w laid out by L (control block, packed values,
+// working flags).
+static void loop_args(int32_t n, const int32_t* row_ptr, const int32_t* col, const uint8_t* acc, map_result* result,
+                      char* w, const Layout& L, LoopArgs& a) {
   std::memset(&a, 0, sizeof(a));
   a.n = n;
   a.ntiles = (int32_t)(((int64_t)n + kTileRows - 1) / kTileRows);
@@ -2759,6 +2783,15 @@ static int loop_common(int32_t n, const int32_t* row_ptr, const int32_t* col, co
   a.result = result;
   word_layout(n, &a.val_mask, &a.tag_mask, &a.tag_shift);
   a.epoch = reinterpret_cast<uint32_t*>(w + L.ctrl + kEpochOff);
+}
+
+static int loop_common(int32_t n, const int32_t* row_ptr, const int32_t* col, const uint8_t* acc, map_result* result,
+                       void* ws, size_t ws_bytes, LoopArgs& a) {
+  if (n < 1 || n > 0x7ffffffe) return MAP_ERANGE;
+  if (!row_ptr || !col || !acc || !result || !ws) return MAP_EINVAL;
+  const Layout L = layout(n);
+  if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return MAP_ENOSPC;
+  loop_args(n, row_ptr, col, acc, result, static_cast<char*>(ws), L, a);
   return MAP_OK;
 }
 
@@ -2821,6 +2854,34 @@ int map_detect(int32_t n, const int32_t* row_ptr, const int32_t* col, const int3
     if (a.push) return MAP_EINVAL;
     a.early = 1;
   }
+  return launch_loop(a, reinterpret_cast<hipStream_t>(stream));
+}
+
+int map_detect_noalloc(int32_t n, const int32_t* row_ptr, const int32_t* col, const uint8_t* accepting0,
+                       map_result* result, uint64_t* trace, int32_t trace_cap, uint8_t* accepting_out,
+                       int32_t max_iterations, uint32_t flags, void* stream) {
+  if (flags & ~kAllFlags) return MAP_EINVAL;
+  if ((flags & MAP_FLAG_PUSH) && !(flags & MAP_FLAG_DENSE_ONLY)) return MAP_EINVAL;
+  if (trace && trace_cap < 0) return MAP_EINVAL;
+  if (n < 1 || n > MAP_NOALLOC_MAX_N) return MAP_ERANGE;
+  if (!row_ptr || !col || !accepting0 || !result) return MAP_EINVAL;
+  const Layout L = layout(n);
+  // Only the control block, packed values and working flags are used.
+  if (L.accw + (size_t)n > kNoAllocBytes) return MAP_ERANGE;
+  char* w = nullptr;
+  int rc = noalloc_scratch_ptr(&w);
+  if (rc) return rc;
+  LoopArgs a;
+  loop_args(n, row_ptr, col, accepting0, result, w, L, a);
+  a.propagate = 0;
+  a.trace = trace;
+  a.trace_cap = trace ? trace_cap : 0;
+  a.acc_out = accepting_out;
+  a.max_iter = max_iterations;
+  a.digest = (trace && !(flags & MAP_FLAG_NO_TRACE_DIGEST)) ? 1 : 0;
+  a.force_stream = (flags & MAP_FLAG_STREAM) ? 1 : 0;
+  a.sync_sweeps = (flags & MAP_FLAG_SYNC_SWEEPS) ? 1 : 0;
+  a.early = (flags & MAP_FLAG_EARLY) ? 1 : 0;
   return launch_loop(a, reinterpret_cast<hipStream_t>(stream));
 }
 

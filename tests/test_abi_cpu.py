@@ -24,6 +24,7 @@ def lib():
     lib.map_build_csr.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.map_propagate.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, u32, vp, sz, vp]
     lib.map_detect.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, i32, vp, i32, u32, vp, sz, vp]
+    lib.map_detect_noalloc.argtypes = [i32, vp, vp, vp, vp, vp, i32, vp, i32, u32, vp]
     lib.map_strerror.argtypes = [ctypes.c_int]
     lib.map_strerror.restype = ctypes.c_char_p
     return lib
@@ -38,6 +39,7 @@ def declared_functions():
 def test_exports_every_declared_symbol(lib):
     names = declared_functions()
     assert names == ["map_batch_workspace_bytes", "map_build_csr", "map_detect", "map_detect_batch",
+                     "map_detect_noalloc",
                      "map_engine_create", "map_engine_destroy", "map_engine_poll", "map_engine_stop",
                      "map_engine_submit", "map_engine_workgroups", "map_job_scratch_bytes", "map_lasso",
                      "map_propagate", "map_strerror", "map_trim", "map_workspace_bytes"]
@@ -95,6 +97,21 @@ def test_host_side_errors_without_device(lib):
     # MAP_FLAG_EARLY with MAP_FLAG_PUSH (frontier rounds) is refused before anything is enqueued
     assert lib.map_detect(5, fake, fake, fake, fake, fake, fake, None, 0, None, 0, 0x30, fake, big, None) == MAP_EINVAL
     assert lib.map_detect(5, fake, fake, fake, fake, fake, fake, None, 0, None, 0, 0x40, fake, big, None) == MAP_EINVAL
+
+
+def test_noalloc_host_side_errors_without_device(lib):
+    fake = ctypes.c_void_p(0x1000)
+    max_n = 1 << 22  # MAP_NOALLOC_MAX_N
+    # sizes beyond the fixed scratch, and empty graphs
+    assert lib.map_detect_noalloc(max_n + 1, fake, fake, fake, fake, None, 0, None, 0, 0, None) == MAP_ERANGE
+    assert lib.map_detect_noalloc(0, fake, fake, fake, fake, None, 0, None, 0, 0, None) == MAP_ERANGE
+    # null pointers, unknown flags, frontier sweeps (no transposed CSR), negative trace capacity
+    assert lib.map_detect_noalloc(5, None, fake, fake, fake, None, 0, None, 0, 0, None) == MAP_EINVAL
+    assert lib.map_detect_noalloc(5, fake, fake, None, fake, None, 0, None, 0, 0, None) == MAP_EINVAL
+    assert lib.map_detect_noalloc(5, fake, fake, fake, None, None, 0, None, 0, 0, None) == MAP_EINVAL
+    assert lib.map_detect_noalloc(5, fake, fake, fake, fake, None, 0, None, 0, 0x80, None) == MAP_EINVAL
+    assert lib.map_detect_noalloc(5, fake, fake, fake, fake, None, 0, None, 0, 0x10, None) == MAP_EINVAL
+    assert lib.map_detect_noalloc(5, fake, fake, fake, fake, fake, -1, None, 0, 0, None) == MAP_EINVAL
 
 
 def test_lasso_host_side_errors_without_device(lib):
