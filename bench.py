@@ -551,6 +551,34 @@ def calibrate_copy(args):
           flush=True)
 
 
+PHASE_NAMES = ("setup", "remote_pass", "lds_passes", "stream_tiles", "report", "wait", "detect_strip", "other")
+
+
+def phase_table(ph, iterations):
+    """Per-phase breakdown of one loop-kernel launch from the measurement build's
+    clocks (100 MHz ticks per workgroup): the mean over workgroups of each
+    phase's time, its share, and the per-iteration and per-sweep figures."""
+    ph = ph.astype(np.float64)
+    nb = ph.shape[0]
+    ms = ph[:, :8].mean(axis=0) / 1e5          # ticks of 10 ns -> ms
+    total = float(ms.sum())
+    sweeps = ph[:, 8].mean()
+    quiet = ph[:, 10].mean()
+    lds = ph[:, 9].mean()
+    table = {name: {"ms": round(float(v), 3), "share": round(float(v) / total, 4) if total else None}
+             for name, v in zip(PHASE_NAMES, ms)}
+    return {
+        "workgroups": nb, "launch_ms": round(total, 3), "per_phase": table,
+        "per_workgroup_sweeps": round(float(sweeps), 1), "quiet_sweep_share": round(float(quiet / sweeps), 4)
+        if sweeps else None,
+        "lds_passes_per_sweep": round(float(lds / sweeps), 3) if sweeps else None,
+        "us_per_iteration": round(total * 1e3 / iterations, 2) if iterations else None,
+        "us_per_sweep": {"remote_pass": round(float(ms[1]) * 1e3 / sweeps, 3) if sweeps else None,
+                         "lds_passes": round(float(ms[2]) * 1e3 / sweeps, 3) if sweeps else None},
+        "us_per_lds_pass": round(float(ms[2]) * 1e3 / lds, 3) if lds else None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -565,6 +593,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=4096, help="graphs in the config-4 batch")
     ap.add_argument("--line-batch", type=int, default=512,
                     help="single-graph line: also run the first N config-4 graphs batched vs plain (0: skip)")
+    ap.add_argument("--phases", action="store_true",
+                    help="load the phase-clock measurement build and add the per-phase breakdown of the last launch")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a plain copy of known size and exit")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--serve-count", type=int, default=1000, help="queries in the config-5 stream")
@@ -594,6 +624,8 @@ def main():
         bench_onthefly(args)
         return
 
+    if args.phases:
+        os.environ["MAPCHECK_LIB"] = os.path.join(ROOT, "paper_0912_2555_amd", "libmapcheck_phases.so")
     import torch
     import paper_0912_2555_amd as mc
 
@@ -677,6 +709,8 @@ def main():
                                      "bytes_per_launch": int(dense_bytes),
                                      "accounting": "whole-graph sweeps * (4(N+1)+4E+8N+N/8) + K*4N per launch"}},
     }
+    if args.phases:
+        out["phases"] = phase_table(mc.phase_counters(), k)
     if args.line_batch > 0:
         torch.cuda.synchronize()
         del ws, row_ptr, col, src, dst

@@ -377,6 +377,18 @@ int map_engine_stop(map_engine *e);
 /* Stop, wait until the kernel has exited, and free the engine. */
 int map_engine_destroy(map_engine *e);
 
+/* Measurement build only (libmapcheck_phases.so, compiled with
+ * -DMAPCHECK_PHASES): per-workgroup phase clocks of the last map_propagate /
+ * map_detect launch, 16 uint64 per workgroup in workgroup order: device
+ * wall-clock ticks (100 MHz) spent in set-up, remote passes, LDS passes,
+ * streamed tiles, change reports (barriers in barrier mode), waiting for work,
+ * detect and strip (with its barrier), and the rest; then the counts of sweeps,
+ * LDS passes, quiet sweeps and iterations; 4 words unused.  Copies
+ * min(*blocks, max_blocks) workgroups to host memory `out` (synchronous, after
+ * the launch has finished) and sets *blocks to the launch's workgroup count.
+ * MAP_EINVAL in the normal build. */
+int map_phase_counters(uint64_t *out, int32_t max_blocks, int32_t *blocks);
+
 /* Static description of a status code. */
 const char *map_strerror(int status);
 

@@ -32,7 +32,9 @@ import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libmapcheck.so")
+# MAPCHECK_LIB may name the phase-clock measurement build of the same source
+# (libmapcheck_phases.so); either way a missing library is an import error.
+LIB_PATH = os.environ.get("MAPCHECK_LIB") or os.path.join(_PKG, "libmapcheck.so")
 
 MAP_OK = 0
 MAP_EINVAL = -1
@@ -55,7 +57,7 @@ MAP_NOALLOC_MAX_N = 1 << 22
 EXPORTS = ("map_workspace_bytes", "map_build_csr", "map_propagate", "map_detect", "map_batch_workspace_bytes",
            "map_detect_batch", "map_job_scratch_bytes", "map_engine_create", "map_engine_workgroups",
            "map_engine_submit", "map_engine_poll", "map_engine_stop", "map_engine_destroy", "map_lasso",
-           "map_trim", "map_strerror", "map_detect_noalloc")
+           "map_trim", "map_strerror", "map_detect_noalloc", "map_phase_counters")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python paper_0912_2555_amd/build.py` "
@@ -95,6 +97,8 @@ _lib.map_engine_stop.argtypes = [_vp]
 _lib.map_engine_stop.restype = ctypes.c_int
 _lib.map_engine_destroy.argtypes = [_vp]
 _lib.map_engine_destroy.restype = ctypes.c_int
+_lib.map_phase_counters.argtypes = [_vp, _i32, _vp]
+_lib.map_phase_counters.restype = ctypes.c_int
 _lib.map_strerror.argtypes = [ctypes.c_int]
 _lib.map_strerror.restype = ctypes.c_char_p
 
@@ -181,6 +185,15 @@ def map_detect_noalloc(n, row_ptr, col, accepting0, result, trace, accepting_out
     cap = 0 if trace is None else int(trace.shape[0])
     return _lib.map_detect_noalloc(n, _ptr(row_ptr), _ptr(col), _ptr(accepting0), _ptr(result), _ptr(trace), cap,
                                    _ptr(accepting_out), max_iterations, flags, _stream(stream))
+
+
+def phase_counters(max_blocks: int = 2048) -> np.ndarray:
+    """Phase clocks of the last loop-kernel launch (measurement build only):
+    uint64[workgroups, 16], columns as map_phase_counters documents."""
+    out = np.zeros((max_blocks, 16), dtype=np.uint64)
+    nb = ctypes.c_int32(0)
+    _check(_lib.map_phase_counters(out.ctypes.data, max_blocks, ctypes.byref(nb)), "map_phase_counters")
+    return out[:min(nb.value, max_blocks)].copy()
 
 
 def map_lasso(n, row_ptr, col, witness, init, path, result, ws, stream=None) -> int:

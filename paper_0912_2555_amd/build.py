@@ -23,18 +23,26 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+# The measurement build: the same source with per-workgroup phase clocks in the
+# loop kernel (map_phase_counters), loaded instead of the library only when
+# MAPCHECK_LIB names it.
+LIB_PHASES = os.path.join(PKG, "libmapcheck_phases.so")
+
+
+def build(verbose: bool = False, phases: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp, SRC]
+    lib = LIB_PHASES if phases else LIB
+    tmp = lib + ".tmp"
+    extra = ["-DMAPCHECK_PHASES"] if phases else []
+    cmd = [hipcc, *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-o", tmp, SRC]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed to build libmapcheck.so")
-    os.replace(tmp, LIB)
-    return LIB
+        raise RuntimeError(f"hipcc failed to build {os.path.basename(lib)}")
+    os.replace(tmp, lib)
+    return lib
 
 
 EXAMPLE_SRC = os.path.join(PKG, "examples", "detect.c")
@@ -61,4 +69,5 @@ def build_example(verbose: bool = False) -> str:
 
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build(verbose=True, phases=True))
     print(build_example(verbose=True))

@@ -361,6 +361,49 @@ __shared__ BlockLds g_lds;
 // its own id (0: none), found by a scan of the block's rows after each sweep.
 __shared__ uint32_t g_early;
 
+#ifdef MAPCHECK_PHASES
+// Phase clocks of the loop kernel, in a build made only to measure where the
+// time goes (libmapcheck_phases.so): thread 0 of each block adds the device
+// wall-clock ticks since its previous mark to the phase a mark names, and counts
+// events; the block writes its totals to g_phase_out when it finishes.
+enum PhaseSlot {
+  kPhSetup, kPhRemote, kPhLocal, kPhStream, kPhReport, kPhWait, kPhDetect, kPhOther,
+  kPhSweeps, kPhLocalPasses, kPhQuiet, kPhIters, kPhSlots = 16
+};
+__shared__ uint64_t g_ph[kPhSlots];
+__shared__ uint64_t g_ph_t;
+__device__ uint64_t g_phase_out[kMaxBlocks * kPhSlots];
+__device__ __forceinline__ void ph_start() {
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < kPhSlots; ++i) g_ph[i] = 0;
+    g_ph_t = wall_clock64();
+  }
+}
+__device__ __forceinline__ void ph_mark(int slot) {
+  if (threadIdx.x == 0) {
+    const uint64_t t = wall_clock64();
+    g_ph[slot] += t - g_ph_t;
+    g_ph_t = t;
+  }
+}
+__device__ __forceinline__ void ph_count(int slot, uint64_t d) {
+  if (threadIdx.x == 0) g_ph[slot] += d;
+}
+__device__ __forceinline__ void ph_store(int b) {
+  if (threadIdx.x == 0 && b < kMaxBlocks)
+    for (int i = 0; i < kPhSlots; ++i) g_phase_out[(size_t)b * kPhSlots + i] = g_ph[i];
+}
+#define PH_START() ph_start()
+#define PH_MARK(slot) ph_mark(slot)
+#define PH_COUNT(slot, d) ph_count((slot), (d))
+#define PH_STORE(b) ph_store(b)
+#else
+#define PH_START() ((void)0)
+#define PH_MARK(slot) ((void)0)
+#define PH_COUNT(slot, d) ((void)0)
+#define PH_STORE(b) ((void)0)
+#endif
+
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -624,6 +667,7 @@ __device__ uint32_t sweep_rows(const LoopArgs& a, const uint8_t* acc, const Wave
   __shared__ uint32_t s_any;
   if (W.resident) {
     uint32_t ch = sweep_resident<kFirst>(a, acc, W, wib, lane, cur, acc_count);
+    PH_MARK(kPhRemote);
     if (threadIdx.x == 0) s_any = 0;
     __syncthreads();
     if (ch && lane == 0) atomicOr(&s_any, 1u);
@@ -639,6 +683,7 @@ __device__ uint32_t sweep_rows(const LoopArgs& a, const uint8_t* acc, const Wave
         if (lc && lane == 0) atomicOr(&s_any, 1u);
         ch |= lc;
         __syncthreads();
+        PH_COUNT(kPhLocalPasses, 1);
         if (s_any == 0) {
           *local_fix = true;
           break;
@@ -648,6 +693,7 @@ __device__ uint32_t sweep_rows(const LoopArgs& a, const uint8_t* acc, const Wave
       *local_fix = true;
     }
     __syncthreads();  // every thread has read s_any
+    PH_MARK(kPhLocal);
     return ch;
   }
   uint32_t ch = 0;
@@ -665,6 +711,7 @@ __device__ uint32_t sweep_rows(const LoopArgs& a, const uint8_t* acc, const Wave
         ch |= sweep_tile<kFirst>(a, acc, t0, min(W.r1, t0 + kTileRows), g_lds.tile[wib], lane, cur, acc_count);
     }
   }
+  PH_MARK(kPhStream);
   return ch;
 }
 
@@ -763,6 +810,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
 
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = threadIdx.x / kWave;
+  PH_START();
   if (kEarly && threadIdx.x == 0) g_early = 0;  // ordered before its first use by the set-up's barriers
   // Tag epoch of this call: left by the previous call on the workspace (an
   // earlier kernel); block 0 writes the next one only after the first grid
@@ -934,6 +982,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     ok = grid_sync(g, 0, nullptr);
     if (!ok) goto aborted;
     count_prev = read_count((g.gen - 1) % kSets);
+    PH_MARK(kPhSetup);
     if (!a.propagate && count_prev == 0) { left = 0; goto done; }
   }
 
@@ -1096,10 +1145,15 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
         d0 = s_red[1];
         __syncthreads();
       }
+      PH_MARK(kPhOther);
       const uint32_t c1 = sweep_rows<true>(a, acc, W, wib, lane, cur, &nacc, &local_fix);
       s = 1;
       early_scan();
-      if (!report(block_any(c1), d0)) goto aborted;
+      const uint32_t any1 = block_any(c1);
+      if (!report(any1, d0)) goto aborted;
+      PH_MARK(kPhReport);
+      PH_COUNT(kPhSweeps, 1);
+      PH_COUNT(kPhQuiet, any1 ? 0 : 1);
     }
     for (;;) {
       uint32_t d0 = 0;
@@ -1144,13 +1198,18 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
         const uint32_t cmd = s_red[0];
         d0 = s_red[1];
         __syncthreads();
+        PH_MARK(kPhWait);
         if (cmd == 2) goto aborted;
         if (cmd == 1) break;
       }
       const uint32_t c2 = sweep_rows<false>(a, acc, W, wib, lane, cur, nullptr, &local_fix);
       s++;
       early_scan();
-      if (!report(block_any(c2), d0)) goto aborted;
+      const uint32_t any2 = block_any(c2);
+      if (!report(any2, d0)) goto aborted;
+      PH_MARK(kPhReport);
+      PH_COUNT(kPhSweeps, 1);
+      PH_COUNT(kPhQuiet, any2 ? 0 : 1);
     }
     }
     // Asynchronous mode: |A_k| is reduced together with the detect pass (same
@@ -1225,6 +1284,8 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
       nz2 = wave_sum_u32(nz2);
       cnt2 = wave_sum_u32(cnt2);
       if (!sync) cnt_k = cnt2;
+      PH_MARK(kPhDetect);
+      PH_COUNT(kPhIters, 1);
       // MAP_FLAG_EARLY: a published early hit (every block's publication
       // precedes its arrival at the barrier above) is a cycle vertex too.
       if (kEarly) w2 = max(w2, (int32_t)ld_agent(&c->early));
@@ -1296,6 +1357,8 @@ done:
     a.result->accepting_left = a.propagate ? 0 : left;
     a.result->reserved = 0;
   }
+  PH_MARK(kPhOther);
+  PH_STORE(b);
   return;
 
 aborted:
@@ -2542,6 +2605,9 @@ int device_info(DeviceInfo* out) {
   return MAP_OK;
 }
 
+// Grid of the last loop-kernel launch (read by map_phase_counters).
+std::atomic<int> g_last_grid{0};
+
 int launch_loop(LoopArgs& a, hipStream_t stream) {
   DeviceInfo di;
   int rc = device_info(&di);
@@ -2566,6 +2632,7 @@ int launch_loop(LoopArgs& a, hipStream_t stream) {
                        : reinterpret_cast<const void*>(map_loop_kernel<false, false>));
   if (hipLaunchCooperativeKernel(kernel, dim3((unsigned)grid), dim3(kBlock), args, 0, stream) != hipSuccess)
     return MAP_EDEVICE;
+  g_last_grid.store((int)grid);
   return MAP_OK;
 }
 
@@ -3230,6 +3297,24 @@ int map_engine_destroy(map_engine* e) {
   const int rc = hipEventSynchronize(e->exited) == hipSuccess ? MAP_OK : MAP_EDEVICE;
   engine_free(e);
   return rc;
+}
+
+int map_phase_counters(uint64_t* out, int32_t max_blocks, int32_t* blocks) {
+#ifdef MAPCHECK_PHASES
+  if (!out || !blocks || max_blocks < 0) return MAP_EINVAL;
+  const int nb = g_last_grid.load();
+  *blocks = nb;
+  const int k = nb < max_blocks ? nb : max_blocks;
+  if (k > 0 && hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase_out), (size_t)k * kPhSlots * sizeof(uint64_t), 0,
+                                   hipMemcpyDeviceToHost) != hipSuccess)
+    return MAP_EDEVICE;
+  return MAP_OK;
+#else
+  (void)out;
+  (void)max_blocks;
+  (void)blocks;
+  return MAP_EINVAL;
+#endif
 }
 
 const char* map_strerror(int status) {

@@ -42,7 +42,7 @@ def test_exports_every_declared_symbol(lib):
                      "map_detect_noalloc",
                      "map_engine_create", "map_engine_destroy", "map_engine_poll", "map_engine_stop",
                      "map_engine_submit", "map_engine_workgroups", "map_job_scratch_bytes", "map_lasso",
-                     "map_propagate", "map_strerror", "map_trim", "map_workspace_bytes"]
+                     "map_phase_counters", "map_propagate", "map_strerror", "map_trim", "map_workspace_bytes"]
     for name in names:
         assert hasattr(lib, name), name
 
