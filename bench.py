@@ -561,12 +561,14 @@ def phase_table(ph, iterations):
     ph = ph.astype(np.float64)
     nb = ph.shape[0]
     ms = ph[:, :8].mean(axis=0) / 1e5          # ticks of 10 ns -> ms
-    total = float(ms.sum())
+    total = float(ms.sum()) + float(ph[:, 12].mean() / 1e5)
     sweeps = ph[:, 8].mean()
     quiet = ph[:, 10].mean()
     lds = ph[:, 9].mean()
     table = {name: {"ms": round(float(v), 3), "share": round(float(v) / total, 4) if total else None}
              for name, v in zip(PHASE_NAMES, ms)}
+    rw = float(ph[:, 12].mean() / 1e5)
+    table["remote_pass_wait"] = {"ms": round(rw, 3), "share": round(rw / total, 4) if total else None}
     return {
         "workgroups": nb, "launch_ms": round(total, 3), "per_phase": table,
         "per_workgroup_sweeps": round(float(sweeps), 1), "quiet_sweep_share": round(float(quiet / sweeps), 4)

@@ -383,7 +383,9 @@ int map_engine_destroy(map_engine *e);
  * wall-clock ticks (100 MHz) spent in set-up, remote passes, LDS passes,
  * streamed tiles, change reports (barriers in barrier mode), waiting for work,
  * detect and strip (with its barrier), and the rest; then the counts of sweeps,
- * LDS passes, quiet sweeps and iterations; 4 words unused.  Copies
+ * LDS passes, quiet sweeps and iterations; then the ticks spent waiting, after
+ * a resident remote pass, for the workgroup's other waves to finish theirs;
+ * 3 words unused.  Copies
  * min(*blocks, max_blocks) workgroups to host memory `out` (synchronous, after
  * the launch has finished) and sets *blocks to the launch's workgroup count.
  * MAP_EINVAL in the normal build. */

@@ -368,7 +368,7 @@ __shared__ uint32_t g_early;
 // events; the block writes its totals to g_phase_out when it finishes.
 enum PhaseSlot {
   kPhSetup, kPhRemote, kPhLocal, kPhStream, kPhReport, kPhWait, kPhDetect, kPhOther,
-  kPhSweeps, kPhLocalPasses, kPhQuiet, kPhIters, kPhSlots = 16
+  kPhSweeps, kPhLocalPasses, kPhQuiet, kPhIters, kPhRemoteWait, kPhSlots = 16
 };
 __shared__ uint64_t g_ph[kPhSlots];
 __shared__ uint64_t g_ph_t;
@@ -603,12 +603,70 @@ __device__ uint32_t local_pass(const LoopArgs& a, const WaveRows& W, int lane, u
   return __ballot(changed) != 0;
 }
 
+// kBal: the balanced layout of the resident slice, used by the asynchronous
+// bodies.  Its in-block edge entries carry the successor's row offset in the
+// block (low 16 bits) and the edge's own row offset in the wave (high 16 bits);
+// otherwise an entry is the successor's row offset alone.
+__device__ __forceinline__ uint32_t in_succ(uint32_t e) { return e & 0xffffu; }
+__device__ __forceinline__ uint32_t in_row(uint32_t e) { return e >> 16; }
+
+// Resident mode, edges to rows of this block, balanced over the lanes (kBal).
+// The wave's rows are taken in groups of 64 in the order values travel, so a
+// group sees the rows the groups before it raised in the same pass.  A group's
+// in-block edges are contiguous (grouped by row) and the lanes share them
+// evenly: lane l folds edges l, l + 64, ... into the group's per-row maxima
+// with an LDS atomic max, so a row of high degree costs its group a few more
+// edges per lane instead of holding up one lane for all of them.  Every
+// in-block row carries the current iteration's tag here (the reset sweep wrote
+// them all before the first pass), so no tag is compared.  Returns nonzero
+// (wave-uniform) if some row grew.
+__device__ uint32_t local_pass_bal(const LoopArgs& a, const WaveRows& W, int wib, int lane) {
+  ResLds& R = g_lds.res;
+  uint32_t* best = R.best[wib];
+  g_u32* pv = (g_u32*)a.pv;
+  const uint32_t vmask = a.val_mask, base = (uint32_t)W.rb0;
+  const int32_t nrow = (int32_t)(W.r1 - W.r0), r0 = (int32_t)(W.r0 - W.rb0);
+  uint32_t changed = 0;
+  for (int jj = 0; jj < kResRowsPerLane; ++jj) {
+    const int32_t g0 = row_step(W, jj) * kWave;  // first row of the group in the wave
+    if (g0 >= nrow) continue;                    // wave-uniform
+    const int32_t g1 = min(g0 + kWave, nrow);
+    const int32_t k0 = R.lrow[r0 + g0];
+    const int32_t k1 = g1 < nrow ? (int32_t)R.lrow[r0 + g1] : W.we1;
+    best[g0 + lane] = 0;
+    wave_lds_sync();
+    for (int32_t k = k0 + lane; k < k1; k += kWave) {
+      const uint32_t e = R.e[k];
+      const uint32_t t = in_succ(e);
+      const uint32_t x = R.pv[t];
+      const uint32_t m = x & vmask, id = base + t + 1u;
+      const uint32_t sv = (x & kAccBit) ? max(m, id) : m;
+      if (sv) atomicMax(&best[in_row(e)], sv);
+    }
+    wave_lds_sync();
+    const int32_t i = g0 + lane;
+    if (i < g1) {
+      const int32_t li = r0 + i;
+      const uint32_t b = best[i];
+      const uint32_t old = R.pv[li];
+      if (b > (old & vmask)) {
+        const uint32_t x = (old & ~vmask) | b;
+        pv[(int64_t)base + li] = x;
+        R.pv[li] = x;
+        changed = 1;
+      }
+    }
+    wave_lds_sync();
+  }
+  return __ballot(changed) != 0;
+}
+
 // Resident mode: the pass over the wave's edges to other blocks' rows.
 // kFirst: the reset sweep, which also folds the in-block edges (successors
 // send their id if accepting) and writes every row.  Otherwise a row is
 // written only when its value grows.  Returns nonzero (wave-uniform) if some
 // row changed.
-template <bool kFirst>
+template <bool kFirst, bool kBal>
 __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, const WaveRows& W, int wib, int lane,
                                    uint32_t cur, uint32_t* acc_count) {
   ResLds& R = g_lds.res;
@@ -621,6 +679,15 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, const 
   for (int j = 0; j < kResRowsPerLane; ++j) best[lane + j * kWave] = 0;
   wave_lds_sync();
   gather_range<kFirst ? 0 : 1>(acc, W.we0, W.wr, best, a, lane, cur);
+  if (kFirst && kBal) {
+    // In-block successors send their id if accepting: folded like the remote
+    // edges, shared evenly over the lanes.
+    for (int32_t k = W.wr + lane; k < W.we1; k += kWave) {
+      const uint32_t e = R.e[k];
+      const uint32_t x = sent_first(acc, (int32_t)(base + in_succ(e)));
+      if (x) atomicMax(&best[in_row(e)], x);
+    }
+  }
   wave_lds_sync();
   uint32_t changed = 0, nacc = 0;
 #pragma unroll
@@ -631,8 +698,10 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, const 
       const int64_t v = (int64_t)base + li;
       uint32_t b = best[i];
       if (kFirst) {
-        const int32_t k1 = i + 1 < nrow ? (int32_t)R.lrow[li + 1] : W.we1;
-        for (int32_t k = R.lrow[li]; k < k1; ++k) b = max(b, sent_first(acc, (int32_t)(base + R.e[k])));
+        if (!kBal) {
+          const int32_t k1 = i + 1 < nrow ? (int32_t)R.lrow[li + 1] : W.we1;
+          for (int32_t k = R.lrow[li]; k < k1; ++k) b = max(b, sent_first(acc, (int32_t)(base + R.e[k])));
+        }
         uint32_t isacc = gacc[v] ? 1u : 0u;
         nacc += isacc;
         const uint32_t x = (isacc << 31) | cur | b;
@@ -661,12 +730,12 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, const 
 // records that the last LDS pass changed nothing: while it holds and the first
 // pass changes nothing, the block's values are at the fixpoint of the values
 // gathered, and the LDS passes are skipped.
-template <bool kFirst>
+template <bool kFirst, bool kBal>
 __device__ uint32_t sweep_rows(const LoopArgs& a, const uint8_t* acc, const WaveRows W, int wib, int lane,
                                uint32_t cur, uint32_t* acc_count, bool* local_fix) {
   __shared__ uint32_t s_any;
   if (W.resident) {
-    uint32_t ch = sweep_resident<kFirst>(a, acc, W, wib, lane, cur, acc_count);
+    uint32_t ch = sweep_resident<kFirst, kBal>(a, acc, W, wib, lane, cur, acc_count);
     PH_MARK(kPhRemote);
     if (threadIdx.x == 0) s_any = 0;
     __syncthreads();
@@ -674,12 +743,13 @@ __device__ uint32_t sweep_rows(const LoopArgs& a, const uint8_t* acc, const Wave
     __syncthreads();
     const bool run = kFirst || s_any != 0 || !*local_fix;
     *local_fix = false;
+    PH_MARK(kPhRemoteWait);
     if (run) {
       for (int p = 0; p < kLocalPasses; ++p) {
         __syncthreads();  // every thread has read s_any; the previous pass's LDS values are complete
         if (threadIdx.x == 0) s_any = 0;
         __syncthreads();
-        const uint32_t lc = local_pass(a, W, lane, cur);
+        const uint32_t lc = kBal ? local_pass_bal(a, W, wib, lane) : local_pass(a, W, lane, cur);
         if (lc && lane == 0) atomicOr(&s_any, 1u);
         ch |= lc;
         __syncthreads();
@@ -810,6 +880,9 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
 
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = threadIdx.x / kWave;
+  // The asynchronous bodies use the balanced layout of the resident slice and
+  // LDS pass; the barrier-mode bodies keep the per-lane row fold.
+  constexpr bool kBal = kAsync;
   PH_START();
   if (kEarly && threadIdx.x == 0) g_early = 0;  // ordered before its first use by the set-up's barriers
   // Tag epoch of this call: left by the previous call on the workspace (an
@@ -900,7 +973,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
           const uint64_t mr = __ballot(rem);
           if (rem) S.res.e[W.we0 + nrem + __popcll(mr & below)] = ((uint32_t)t << 8) | off;
           nrem += __popcll(mr);
-          if (act && !rem) S.res.e[lpos++] = (uint32_t)t - base;
+          if (act && !rem) S.res.e[lpos++] = (kBal ? (off << 16) : 0u) | ((uint32_t)t - base);
           k += act ? 1 : 0;
         }
       }
@@ -1146,7 +1219,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
         __syncthreads();
       }
       PH_MARK(kPhOther);
-      const uint32_t c1 = sweep_rows<true>(a, acc, W, wib, lane, cur, &nacc, &local_fix);
+      const uint32_t c1 = sweep_rows<true, kBal>(a, acc, W, wib, lane, cur, &nacc, &local_fix);
       s = 1;
       early_scan();
       const uint32_t any1 = block_any(c1);
@@ -1202,7 +1275,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
         if (cmd == 2) goto aborted;
         if (cmd == 1) break;
       }
-      const uint32_t c2 = sweep_rows<false>(a, acc, W, wib, lane, cur, nullptr, &local_fix);
+      const uint32_t c2 = sweep_rows<false, kBal>(a, acc, W, wib, lane, cur, nullptr, &local_fix);
       s++;
       early_scan();
       const uint32_t any2 = block_any(c2);
