@@ -21,6 +21,30 @@ def pytest_sessionstart(session):
     synth.build(force=False)
 
 
+C_EXAMPLE = os.path.join(ROOT, "paper_0912_2555_amd", "examples", "detect")
+C_EXAMPLE_TEST = "test_c_example_runs"
+# Outcome of the C usage example (a child process), run once when the GPU test
+# that checks it is selected, at the end of collection: before any test of
+# this process touches the GPU, whatever order the test files run in.  (A
+# second process's cooperative launch was refused once this process had made
+# cooperative launches of its own.)
+c_example_outcome = {}
+
+
+def pytest_collection_finish(session):
+    if not any(item.name == C_EXAMPLE_TEST for item in session.items):
+        return
+    import subprocess
+    if not os.path.exists(C_EXAMPLE):
+        c_example_outcome["error"] = "the C example is not built (python paper_0912_2555_amd/build.py)"
+        return
+    try:
+        r = subprocess.run([C_EXAMPLE], capture_output=True, text=True, timeout=120)
+        c_example_outcome.update(returncode=r.returncode, stdout=r.stdout, stderr=r.stderr)
+    except subprocess.TimeoutExpired:
+        c_example_outcome["error"] = "the C example did not finish within 120 s"
+
+
 def read_golden(name):
     """Parse a tests/golden text fixture into {key: [rows of ints]}."""
     out = {}

@@ -6,12 +6,9 @@ oracle so that the example's own expectations are pinned too.
 
 The example runs as a child process and launches cooperative kernels.  A
 second process's cooperative launch was refused once this test process had
-made cooperative launches of its own (the other GPU test files), so this file
-is named to run first, before anything here touches the GPU; it uses no GPU
-in this process itself."""
-import os
-import subprocess
-
+made cooperative launches of its own, so conftest.py runs the example at the
+end of collection, before any test touches the GPU, and this test checks the
+outcome it recorded; the order of the test files does not matter."""
 import numpy as np
 import pytest
 
@@ -20,8 +17,6 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-EXAMPLE = os.path.join(ROOT, "paper_0912_2555_amd", "examples", "detect")
 
 
 def test_expected_values_agree_with_the_oracle():
@@ -40,9 +35,10 @@ def test_expected_values_agree_with_the_oracle():
 
 
 def test_c_example_runs():
-    assert os.path.exists(EXAMPLE), "the C example is not built (python paper_0912_2555_amd/build.py)"
-    r = subprocess.run([EXAMPLE], capture_output=True, text=True, timeout=120)
-    print(r.stdout, r.stderr, flush=True)
-    assert r.returncode == 0
-    lines = r.stdout.strip().splitlines()
+    from conftest import c_example_outcome as out
+    assert "error" not in out, out.get("error")
+    assert out, "the C example was not run at the end of collection"
+    print(out["stdout"], out["stderr"], flush=True)
+    assert out["returncode"] == 0
+    lines = out["stdout"].strip().splitlines()
     assert len(lines) == 2 and all(line.endswith(" ok") for line in lines)
