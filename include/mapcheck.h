@@ -86,6 +86,14 @@ extern "C" {
  * MAP_FLAG_SYNC_SWEEPS were set.  Ignored by map_propagate; MAP_EINVAL together
  * with MAP_FLAG_PUSH (unless MAP_FLAG_DENSE_ONLY is set as well). */
 #define MAP_FLAG_EARLY 0x20u
+/* map_propagate, map_detect: when every workgroup streams its rows (the graph
+ * is too large for the rows to be staged on chip, or MAP_FLAG_STREAM is set)
+ * and frontier sweeps and MAP_FLAG_EARLY are not used, the sweeps run with a
+ * grid barrier after each and gather a successor's value only if it grew in
+ * the previous sweep (bitmaps of one bit per vertex in the workspace); the
+ * results are the same.  This flag turns that filter off (the previous
+ * control applies: asynchronous unless MAP_FLAG_SYNC_SWEEPS). */
+#define MAP_FLAG_NO_FILTER 0x40u
 
 /* Result of map_propagate / map_detect, written to device memory (32 bytes). */
 typedef struct map_result {

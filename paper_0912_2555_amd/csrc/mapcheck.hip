@@ -52,7 +52,7 @@ constexpr int kSortPerLane = kSortSlots / kWave;
 static_assert(kSortSlots >= kWave * kGatherBatch, "sort must cover a gather batch");
 constexpr uint32_t kAllFlags =
     MAP_FLAG_DENSE_ONLY | MAP_FLAG_NO_TRACE_DIGEST | MAP_FLAG_STREAM | MAP_FLAG_SYNC_SWEEPS | MAP_FLAG_PUSH |
-    MAP_FLAG_EARLY;
+    MAP_FLAG_EARLY | MAP_FLAG_NO_FILTER;
 constexpr uint32_t kAccBit = 0x80000000u;
 
 // Global-memory views of device pointers, for out-of-line functions where the
@@ -309,6 +309,13 @@ struct LoopArgs {
   const int32_t* rcol;
   int32_t* front[2];     // push: frontier lists, int32[n] each
   uint32_t* mark;        // push: round in which a vertex last joined a frontier
+  // Filtered stream sweeps (every block streams, barrier per sweep): three
+  // change bitmaps of one bit per vertex (the rows that grew in a sweep) and
+  // the bitmap of the current accepting set; null where no workspace holds them.
+  uint32_t* chg;         // [3][words]
+  uint32_t* accb;        // [words]
+  int64_t words;         // 32-bit words per bitmap
+  int32_t filt;          // 1: run the filtered stream kernel
 };
 
 // Row ownership: the rows are cut into one contiguous range per block and,
@@ -785,6 +792,130 @@ __device__ uint32_t sweep_rows(const LoopArgs& a, const uint8_t* acc, const Wave
   return ch;
 }
 
+// Sets, with one atomic per 32-bit word, the bits of bitmap `mark` for the
+// rows v0 + l (l = 0..63) whose lane l is set in m (wave-uniform m).
+__device__ __forceinline__ void mark_rows(uint32_t* mark, int64_t v0, unsigned long long m, int lane) {
+  if (m == 0) return;
+  const uint32_t sh = (uint32_t)(v0 & 31);
+  const int64_t w0 = v0 >> 5;
+  const unsigned long long lo = m << sh;
+  uint32_t part = 0;
+  if (lane == 0) part = (uint32_t)lo;
+  else if (lane == 1) part = (uint32_t)(lo >> 32);
+  else if (lane == 2) part = sh ? (uint32_t)(m >> (64 - sh)) : 0u;
+  if (part) atomicOr(&mark[w0 + lane], part);
+}
+
+__device__ __forceinline__ bool bit_set(const uint32_t* b, uint32_t v) { return (b[v >> 5] >> (v & 31)) & 1u; }
+
+// Filtered stream mode (every block streams its rows, a grid barrier after
+// every sweep): like sweep_tile, but an edge's successor w is gathered only if
+// its bit is set in `keep` -- in the reset sweep the accepting set (w sends its
+// id), later the rows that grew in the previous sweep (w sends its value).  A
+// successor left out either sends nothing new (not accepting) or has not grown
+// since the previous sweep, whose rows already folded in its value: the
+// fixpoint is unchanged.  The rows that grow (in the reset sweep: that get a
+// nonzero value) are set in `mark` for the next sweep.
+template <bool kFirst>
+__device__ uint32_t sweep_tile_filt(const LoopArgs& a, const uint8_t* acc, int64_t r0, int64_t r1, TileLds& L,
+                                    int lane, uint32_t cur, uint32_t* acc_count, const uint32_t* keep,
+                                    uint32_t* mark) {
+  const int nr = (int)(r1 - r0);
+  g_ci32* row_ptr = (g_ci32*)a.row_ptr;
+  g_ci32* colp = (g_ci32*)a.col;
+  g_u32* pv = (g_u32*)a.pv;
+  g_cu8* gacc = (g_cu8*)acc;
+  const uint32_t n = (uint32_t)a.n, vmask = a.val_mask, tmask = a.tag_mask;
+  for (int i = lane; i <= nr; i += kWave) L.rp[i] = __builtin_nontemporal_load(row_ptr + r0 + i);
+  wave_lds_sync();
+  const int32_t e0 = L.rp[0], e1 = L.rp[nr];
+  int32_t lo[kRowsPerLane], hi[kRowsPerLane];
+  uint32_t best[kRowsPerLane], old[kRowsPerLane];
+#pragma unroll
+  for (int j = 0; j < kRowsPerLane; ++j) {
+    int r = lane + j * kWave;
+    lo[j] = r < nr ? L.rp[r] : 0;
+    hi[j] = r < nr ? L.rp[r + 1] : 0;
+    best[j] = 0;
+    old[j] = (!kFirst && r < nr) ? pv[r0 + r] : 0u;
+  }
+  for (int32_t c0 = e0; c0 < e1; c0 += kTileEdges) {
+    const int cnt = (int)min((int64_t)kTileEdges, (int64_t)e1 - c0);
+    uint32_t w[kEdgesPerLane];
+#pragma unroll
+    for (int u = 0; u < kEdgesPerLane; ++u) {
+      int i = lane + u * kWave;
+      w[u] = i < cnt ? (uint32_t)__builtin_nontemporal_load(colp + c0 + i) : 0xffffffffu;
+    }
+#pragma unroll
+    for (int u = 0; u < kEdgesPerLane; ++u) {
+      int i = lane + u * kWave;
+      uint32_t x = 0;
+      if (w[u] < n && bit_set(keep, w[u])) x = kFirst ? w[u] + 1u : sent_word(pv[w[u]], (int32_t)w[u], cur, vmask, tmask);
+      if (i < cnt) L.val[i] = x;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < kRowsPerLane; ++j) {
+      int b = max(lo[j] - c0, 0), e = min(hi[j] - c0, cnt);
+      uint32_t m = best[j];
+      for (int k = b; k < e; ++k) m = max(m, L.val[k]);
+      best[j] = m;
+    }
+    wave_lds_sync();
+  }
+  uint32_t changed = 0, nacc = 0;
+#pragma unroll
+  for (int j = 0; j < kRowsPerLane; ++j) {
+    int r = lane + j * kWave;
+    bool grew = false;
+    if (r < nr) {
+      int64_t v = r0 + r;
+      if (kFirst) {
+        uint32_t isacc = gacc[v] ? 1u : 0u;
+        nacc += isacc;
+        pv[v] = (isacc << 31) | cur | best[j];
+        changed |= (best[j] | isacc) != 0;
+        grew = best[j] != 0;
+      } else if (best[j] > (old[j] & vmask)) {
+        pv[v] = (old[j] & ~vmask) | best[j];
+        changed = 1;
+        grew = true;
+      }
+    }
+    mark_rows(mark, r0 + j * kWave, __ballot(grew), lane);
+  }
+  if (acc_count) *acc_count += nacc;
+  return __ballot(changed) != 0;
+}
+
+// One filtered stream sweep of the wave's rows, in tiles in the order values
+// travel (see sweep_rows).
+template <bool kFirst>
+__device__ uint32_t sweep_stream_filt(const LoopArgs& a, const uint8_t* acc, const WaveRows& W, int wib, int lane,
+                                      uint32_t cur, uint32_t* acc_count, const uint32_t* keep, uint32_t* mark) {
+  uint32_t ch = 0;
+  if (W.r1 > W.r0) {
+    const int64_t last = W.r0 + ((W.r1 - W.r0 - 1) / kTileRows) * kTileRows;
+    if (W.ascending) {
+      for (int64_t t0 = W.r0; t0 <= last; t0 += kTileRows)
+        ch |= sweep_tile_filt<kFirst>(a, acc, t0, min(W.r1, t0 + kTileRows), g_lds.tile[wib], lane, cur, acc_count,
+                                      keep, mark);
+    } else {
+      for (int64_t t0 = last; t0 >= W.r0; t0 -= kTileRows)
+        ch |= sweep_tile_filt<kFirst>(a, acc, t0, min(W.r1, t0 + kTileRows), g_lds.tile[wib], lane, cur, acc_count,
+                                      keep, mark);
+    }
+  }
+  PH_MARK(kPhStream);
+  return ch;
+}
+
+// Clears this block's share of the words of bitmap b (word-striped over the grid).
+__device__ __forceinline__ void clear_share(uint32_t* b, int64_t words, int blk, int nb) {
+  for (int64_t i = (int64_t)blk * kBlock + threadIdx.x; i < words; i += (int64_t)nb * kBlock) b[i] = 0u;
+}
+
 // Calls f(v, packed value of v) for every row v of the wave (lane-strided).
 template <typename F>
 __device__ __forceinline__ void for_own_rows(const LoopArgs& a, const WaveRows& W, int lane, F f) {
@@ -871,7 +1002,7 @@ __device__ __forceinline__ uint32_t frontier_append(int32_t* F, uint32_t* cnt, b
 // kAsync selects the fixpoint control at compile time: asynchronous sweeps with
 // quiescence detection, or a grid barrier after every sweep (required for a
 // single block, for untagged values, and with MAP_FLAG_SYNC_SWEEPS).
-template <typename C, bool kAsync, bool kEarly>
+template <typename C, bool kAsync, bool kEarly, bool kFilt = false>
 __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, const int logical) {
   BlockLds& S = g_lds;
   __shared__ uint32_t s_red[kWavesPerBlock];
@@ -905,7 +1036,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     const int32_t eb0 = a.row_ptr[rb0], eb1 = a.row_ptr[rb1];
     // n < 2^24 keeps every staged remote key (successor << 8 | row offset)
     // below 0xffffffff, the padding key of the sort and the gather.
-    W.resident = !a.force_stream && a.n < (1 << 24) && rows_per_wave <= kResWaveRows &&
+    W.resident = !kFilt && !a.force_stream && a.n < (1 << 24) && rows_per_wave <= kResWaveRows &&
                  (int64_t)eb1 - eb0 <= kResEdges;
     W.wr = 0;
     {
@@ -1026,6 +1157,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
 
   uint32_t count_prev = 0;  // |A_k| of the last completed iteration
   uint32_t rtag = 0;        // push: frontier round, the same in every block
+  uint32_t gsw = 0;         // filtered stream sweeps: sweeps so far, the same in every block
   int32_t k = 0;
   int64_t total_sweeps = 0;  // whole-graph sweeps, summed over the iterations
   int32_t status = MAP_OK, found = 0, witness = 0;
@@ -1051,6 +1183,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
         cnt += x;
       }
     }
+    if (kFilt) clear_share(a.chg, 3 * a.words, b, nb);
     block_add_count(cnt, g.gen % kSets);
     ok = grid_sync(g, 0, nullptr);
     if (!ok) goto aborted;
@@ -1064,6 +1197,18 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     // Iteration tag: values written in iteration k carry the tag of k; a
     // reader that finds another tag takes the reset value instead.
     const uint32_t cur = iter_tag(a.tag_mask, a.tag_shift, tbase, k);
+    if (kFilt) {
+      // The accepting set of this iteration as a bitmap (64 vertices per wave
+      // step), complete in every block before the reset sweep reads it.
+      const int64_t gw = (int64_t)b * kWavesPerBlock + wib, nw = (int64_t)nb * kWavesPerBlock;
+      for (int64_t v0 = gw * kWave; v0 < (int64_t)a.n; v0 += nw * kWave) {
+        const int64_t v = v0 + lane;
+        const unsigned long long am = __ballot(v < (int64_t)a.n && acc[v] != 0);
+        const int64_t wi = (v0 >> 5) + lane;
+        if (lane < 2 && wi < a.words) a.accb[wi] = lane ? (uint32_t)(am >> 32) : (uint32_t)am;
+      }
+      if (!grid_sync(g, 0, nullptr)) goto aborted;
+    }
     uint32_t nacc = 0;       // accepting rows of this block in A_k (reset sweep)
     uint32_t cnt_k = 0;      // |A_k|
     int64_t s = 0;           // sweeps of this block in iteration k
@@ -1219,7 +1364,17 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
         __syncthreads();
       }
       PH_MARK(kPhOther);
-      const uint32_t c1 = sweep_rows<true, kBal>(a, acc, W, wib, lane, cur, &nacc, &local_fix);
+      uint32_t c1;
+      if (kFilt) {
+        // Sweep gsw reads the rows that grew in sweep gsw - 1 (the reset sweep:
+        // the accepting set), marks its own in bitmap gsw % 3 and clears
+        // bitmap (gsw + 1) % 3 for the next sweep.
+        clear_share(a.chg + ((gsw + 1) % 3) * a.words, a.words, b, nb);
+        c1 = sweep_stream_filt<true>(a, acc, W, wib, lane, cur, &nacc, a.accb, a.chg + (gsw % 3) * a.words);
+        ++gsw;
+      } else {
+        c1 = sweep_rows<true, kBal>(a, acc, W, wib, lane, cur, &nacc, &local_fix);
+      }
       s = 1;
       early_scan();
       const uint32_t any1 = block_any(c1);
@@ -1275,7 +1430,15 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
         if (cmd == 2) goto aborted;
         if (cmd == 1) break;
       }
-      const uint32_t c2 = sweep_rows<false, kBal>(a, acc, W, wib, lane, cur, nullptr, &local_fix);
+      uint32_t c2;
+      if (kFilt) {
+        clear_share(a.chg + ((gsw + 1) % 3) * a.words, a.words, b, nb);
+        c2 = sweep_stream_filt<false>(a, acc, W, wib, lane, cur, nullptr, a.chg + ((gsw + 2) % 3) * a.words,
+                                      a.chg + (gsw % 3) * a.words);
+        ++gsw;
+      } else {
+        c2 = sweep_rows<false, kBal>(a, acc, W, wib, lane, cur, nullptr, &local_fix);
+      }
       s++;
       early_scan();
       const uint32_t any2 = block_any(c2);
@@ -1443,14 +1606,14 @@ aborted:
 
 // kEarly: MAP_FLAG_EARLY (a separate instantiation, so that the plain loop
 // carries none of its code).
-template <bool kAsync, bool kEarly>
+template <bool kAsync, bool kEarly, bool kFilt = false>
 __global__ void __launch_bounds__(kBlock) map_loop_kernel(LoopArgs a) {
   const int nb = gridDim.x;
   const int b = blockIdx.x;
   // XCD-aware numbering: consecutive hardware block ids land on different
   // XCDs; give each XCD a contiguous range of logical blocks (and rows).
   const int logical = (nb % kMaxGroups == 0) ? (b % kMaxGroups) * (nb / kMaxGroups) + b / kMaxGroups : b;
-  map_body<Ctrl, kAsync, kEarly>(a, a.ctrl, nb, b, logical);
+  map_body<Ctrl, kAsync, kEarly, kFilt>(a, a.ctrl, nb, b, logical);
 }
 
 // ------------------------------------------------------------------ batch --
@@ -1971,6 +2134,10 @@ __device__ LoopArgs gang_args(int32_t n, const int32_t* row_ptr, const int32_t* 
   a.push = 0;
   a.early = (flags & MAP_FLAG_EARLY) ? 1 : 0;
   a.rrow_ptr = nullptr;
+  a.chg = nullptr;
+  a.accb = nullptr;
+  a.words = 0;
+  a.filt = 0;
   a.rcol = nullptr;
   a.front[0] = a.front[1] = nullptr;
   a.mark = nullptr;
@@ -2612,7 +2779,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 bool sizes_ok(int32_t n, int64_t m) { return n >= 1 && n <= 0x7ffffffe && m >= 0 && m <= 0x7fffffff; }
 
 struct Layout {
-  size_t ctrl, pv, accw, front0, front1, mark, aux, cursor, sums, total;
+  size_t ctrl, pv, accw, front0, front1, mark, aux, chg, accb, cursor, sums, total;
+  int64_t words;  // 32-bit words of one vertex bitmap
 };
 
 Layout layout(int32_t n) {
@@ -2636,6 +2804,12 @@ Layout layout(int32_t n) {
   // pruning: removed flags
   L.aux = off;
   off += align256((size_t)n * 4);
+  // filtered stream sweeps: three change bitmaps and the accepting bitmap
+  L.words = ((int64_t)n + 31) / 32;
+  L.chg = off;
+  off += align256((size_t)L.words * 4 * 3);
+  L.accb = off;
+  off += align256((size_t)L.words * 4);
   size_t end_loop = off;
   // CSR build (shares the region after ctrl)
   off = region;
@@ -2698,11 +2872,19 @@ int launch_loop(LoopArgs& a, hipStream_t stream) {
   void* args[] = {&a};
   // MAP_FLAG_EARLY runs with a grid barrier after every sweep (no asynchronous
   // early instantiation exists).
-  const bool async = grid > 1 && !a.sync_sweeps && a.tag_mask != 0 && !a.early;
+  // When no block can stage its slice on chip (or staging is refused) and the
+  // workspace holds the change bitmaps, the filtered stream kernel runs: a
+  // barrier after every sweep, gathers only from rows that grew.
+  const int64_t rpb = ((int64_t)a.n + grid - 1) / grid;
+  const int64_t rpw = (rpb + kWavesPerBlock - 1) / kWavesPerBlock;
+  const bool all_stream = a.force_stream || a.n >= (1 << 24) || rpw > kResWaveRows;
+  a.filt = (a.chg != nullptr && !a.early && !a.push && all_stream) ? 1 : 0;
+  const bool async = !a.filt && grid > 1 && !a.sync_sweeps && a.tag_mask != 0 && !a.early;
   const void* kernel =
       a.early ? reinterpret_cast<const void*>(map_loop_kernel<false, true>)
-              : (async ? reinterpret_cast<const void*>(map_loop_kernel<true, false>)
-                       : reinterpret_cast<const void*>(map_loop_kernel<false, false>));
+      : a.filt ? reinterpret_cast<const void*>(map_loop_kernel<false, false, true>)
+               : (async ? reinterpret_cast<const void*>(map_loop_kernel<true, false>)
+                        : reinterpret_cast<const void*>(map_loop_kernel<false, false>));
   if (hipLaunchCooperativeKernel(kernel, dim3((unsigned)grid), dim3(kBlock), args, 0, stream) != hipSuccess)
     return MAP_EDEVICE;
   g_last_grid.store((int)grid);
@@ -2923,6 +3105,9 @@ static void loop_args(int32_t n, const int32_t* row_ptr, const int32_t* col, con
   a.result = result;
   word_layout(n, &a.val_mask, &a.tag_mask, &a.tag_shift);
   a.epoch = reinterpret_cast<uint32_t*>(w + L.ctrl + kEpochOff);
+  a.chg = reinterpret_cast<uint32_t*>(w + L.chg);
+  a.accb = reinterpret_cast<uint32_t*>(w + L.accb);
+  a.words = L.words;
 }
 
 static int loop_common(int32_t n, const int32_t* row_ptr, const int32_t* col, const uint8_t* acc, map_result* result,
@@ -2965,6 +3150,7 @@ int map_propagate(int32_t n, const int32_t* row_ptr, const int32_t* col, const i
   a.propagate = 1;
   a.force_stream = (flags & MAP_FLAG_STREAM) ? 1 : 0;
   a.sync_sweeps = (flags & MAP_FLAG_SYNC_SWEEPS) ? 1 : 0;
+  if (flags & MAP_FLAG_NO_FILTER) a.chg = nullptr;
   a.map_out = map_out;
   rc = push_setup(a, rrow_ptr, rcol, flags, ws);
   if (rc) return rc;
@@ -2988,6 +3174,7 @@ int map_detect(int32_t n, const int32_t* row_ptr, const int32_t* col, const int3
   a.digest = (trace && !(flags & MAP_FLAG_NO_TRACE_DIGEST)) ? 1 : 0;
   a.force_stream = (flags & MAP_FLAG_STREAM) ? 1 : 0;
   a.sync_sweeps = (flags & MAP_FLAG_SYNC_SWEEPS) ? 1 : 0;
+  if (flags & MAP_FLAG_NO_FILTER) a.chg = nullptr;
   rc = push_setup(a, rrow_ptr, rcol, flags, ws);
   if (rc) return rc;
   if (flags & MAP_FLAG_EARLY) {
@@ -3013,6 +3200,8 @@ int map_detect_noalloc(int32_t n, const int32_t* row_ptr, const int32_t* col, co
   if (rc) return rc;
   LoopArgs a;
   loop_args(n, row_ptr, col, accepting0, result, w, L, a);
+  a.chg = nullptr;  // the fixed scratch holds no change bitmaps: unfiltered sweeps
+  a.accb = nullptr;
   a.propagate = 0;
   a.trace = trace;
   a.trace_cap = trace ? trace_cap : 0;

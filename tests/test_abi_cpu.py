@@ -96,7 +96,7 @@ def test_host_side_errors_without_device(lib):
     assert lib.map_detect(5, fake, fake, None, None, fake, fake, None, 0, None, 0, 0, fake, 8, None) == MAP_ENOSPC
     # MAP_FLAG_EARLY with MAP_FLAG_PUSH (frontier rounds) is refused before anything is enqueued
     assert lib.map_detect(5, fake, fake, fake, fake, fake, fake, None, 0, None, 0, 0x30, fake, big, None) == MAP_EINVAL
-    assert lib.map_detect(5, fake, fake, fake, fake, fake, fake, None, 0, None, 0, 0x40, fake, big, None) == MAP_EINVAL
+    assert lib.map_detect(5, fake, fake, fake, fake, fake, fake, None, 0, None, 0, 0x80, fake, big, None) == MAP_EINVAL
 
 
 def test_noalloc_host_side_errors_without_device(lib):

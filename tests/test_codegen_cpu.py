@@ -24,8 +24,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "paper_0912_2555_amd", "csrc", "mapcheck.hip")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
+# Name prefixes of the asynchronous bodies: map_loop_kernel<true, false, ...>
+# and the gang body of the batch and the engine.
 ASYNC_BODIES = [
-    "_ZN12_GLOBAL__N_115map_loop_kernelILb1ELb0EEEvNS_8LoopArgsE",      # map_loop_kernel<true, false>
+    "_ZN12_GLOBAL__N_115map_loop_kernelILb1ELb0E",
     "_ZN12_GLOBAL__N_119map_body_gang_asyncERKNS_8LoopArgsEPNS_5CtrlTILi256EEEii",
 ]
 
@@ -48,9 +50,11 @@ def asm():
         return open(out).read()
 
 
-def function_body(asm, name):
-    m = re.search(r"^" + re.escape(name) + r":.*?^\.Lfunc_end", asm, re.S | re.M)
-    assert m, f"{name} not found in the device assembly"
+def function_body(asm, prefix):
+    """The assembly of the one function whose symbol starts with `prefix`."""
+    found = re.findall(r"^(" + re.escape(prefix) + r"[\w.$]*):", asm, re.M)
+    assert len(found) == 1, f"{prefix}: expected one function, found {found}"
+    m = re.search(r"^" + re.escape(found[0]) + r":.*?^\.Lfunc_end", asm, re.S | re.M)
     return m.group(0)
 
 

@@ -37,7 +37,7 @@ def accepting_sequence(g, ref):
     """A_1..A_K reconstructed from the oracle's map vectors."""
     acc = g.acc.copy()
     out = []
-    for k in range(ref.iterations):
+    for k in range(min(ref.iterations, len(ref.maps))):
         out.append(acc.copy())
         nz = ref.maps[k][ref.maps[k] != 0]
         acc[nz - 1] = 0
@@ -68,14 +68,14 @@ def check_detect(mc, g, csr=None, max_iterations=0, trace_cap=None, flags=0, ref
     return out, ref
 
 
-def check_propagate_all(mc, g, csr=None, max_k=None):
+def check_propagate_all(mc, g, csr=None, max_k=None, flags=0):
     """Full map vector of every iteration (the oracle's A_k as input)."""
     if csr is None:
         csr = mc.build_csr(g.n, g.src, g.dst)
     ref = oracle.map_detect(g, mode="jacobi" if g.n <= 20000 else "desc", maps_cap=max_k or (g.n_acc + 1))
     accs = accepting_sequence(g, ref)
     for k, acc in enumerate(accs[:max_k]):
-        got, res = mc.propagate(csr, acc)
+        got, res = mc.propagate(csr, acc, flags=flags)
         assert res.status == 0
         assert np.array_equal(got.cpu().numpy(), ref.maps[k]), (g.name, k + 1)
     return ref
@@ -118,14 +118,27 @@ def test_random_graphs(mc, g):
 
 
 @pytest.mark.parametrize("g", [c for c in _random_cases() if c.n >= 64] + [synth.config1(dag=True),
-                               synth.config2(seed=3, n=1 << 15, planted=True)], ids=lambda g: g.name)
-def test_stream_mode(mc, g):
-    """The same results with the CSR streamed every sweep instead of staged on chip."""
+                               synth.config2(seed=3, n=1 << 15, planted=True),
+                               synth.config2(seed=6, n=1 << 14)], ids=lambda g: g.name)
+@pytest.mark.parametrize("filt", [True, False], ids=["filtered", "unfiltered"])
+def test_stream_mode(mc, g, filt):
+    """The same results with the CSR streamed every sweep instead of staged on
+    chip: by default with a barrier per sweep and gathers only from rows that
+    grew in the previous sweep, and with that filter off (asynchronous)."""
+    flags = mc.MAP_FLAG_STREAM | (0 if filt else mc.MAP_FLAG_NO_FILTER)
     csr = mc.build_csr(g.n, g.src, g.dst)
-    check_detect(mc, g, csr, flags=mc.MAP_FLAG_STREAM)
+    check_detect(mc, g, csr, flags=flags)
     ref = oracle.map_detect(g, mode="desc", maps_cap=1)
-    got, res = mc.propagate(csr, g.acc, flags=mc.MAP_FLAG_STREAM)
+    got, res = mc.propagate(csr, g.acc, flags=flags)
     assert res.status == 0 and np.array_equal(got.cpu().numpy(), ref.maps[0])
+
+
+@pytest.mark.parametrize("g", [synth.config3(n=1 << 16), synth.config2(seed=8, n=1 << 13, planted=True),
+                               synth.config1()], ids=lambda g: g.name)
+def test_filtered_stream_full_vectors(mc, g):
+    """Filtered stream sweeps (barrier per sweep, gathers only from rows that
+    grew): the full map vector of every iteration equals the oracle's."""
+    check_propagate_all(mc, g, max_k=8, flags=mc.MAP_FLAG_STREAM)
 
 
 @pytest.mark.parametrize("n,planted", [(1 << 14, False), (1 << 14, True), (1 << 16, False), (1 << 16, True)])
