@@ -59,6 +59,9 @@ WORKLOADS = {
     "onthefly": ("detection on a growing graph: config 2 variant A's edge stream in generation order (grouped by "
                  "source), prefixes of 1/16, 2/16, ... each built, pruned (map_trim) and checked (map_detect) until "
                  "a cycle is found, vs one build + detection of the whole graph", "config2", True),
+    "hub": ("hub rows: a config-3 style DAG with N=2^22 (~16.8M edges) plus four out-hubs of 10^5 edges, one "
+            "graph solved by all workgroups through the batch path with the long-row threshold at its default "
+            "(whole-wave fold) and off (every row folded by its own lane)", "config3", None),
     "lasso": ("counterexample on config 2 variant A: shortest path from vertex 1 to the witness found by "
               "map_detect, then shortest cycle through it (breadth-first search, one cooperative launch)",
               "config2", True),
@@ -271,6 +274,49 @@ def batch_run(args, count, capture=True):
         "exact_vs_plain": exact_vs_plain, "exact_vs_oracle_golden": exact_vs_oracle,
         "found": int(sum(r.found for r in res_b)),
     }
+
+
+def hub_graph():
+    """Config-3 generator at N=2^22 plus four out-hubs of 10^5 edges each."""
+    import synth
+    base = synth.config3(n=1 << 22)
+    rng = np.random.default_rng(21)
+    hubs = [np.stack([np.full(100_000, h, np.int64), rng.integers(1, h, 100_000)], 1)
+            for h in ((1 << 22) - 3, 3 << 20, 1 << 21, 1 << 20)]
+    e = np.concatenate([np.stack([base.src, base.dst], 1)] + hubs).astype(np.int32)
+    return synth.Graph(n=base.n, src=e[:, 0].copy(), dst=e[:, 1].copy(), acc=base.acc, name="hub")
+
+
+def bench_hub(args):
+    """One hub graph through map_detect_batch with a gang of every workgroup:
+    the long-row threshold at its default against off; both exact (oracle)."""
+    import torch
+    import oracle
+    import paper_0912_2555_amd as mc
+    torch.cuda.set_device(0)
+    g = hub_graph()
+    ref = oracle.map_detect(g, mode="desc")
+    csr = mc.build_csr(g.n, g.src, g.dst, transposed=False)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, opt in (("whole_wave_fold", 0), ("lane_fold", mc.MAP_GRAPH_HUB_MASK)):
+        b = mc.Batch([csr], [g.acc], gang=[1024], options=[opt])
+        times = []
+        for rep in range(args.warmup + args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            b.results.zero_()
+            e0.record(stream)
+            b.launch()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if rep >= args.warmup:
+                times.append(e0.elapsed_time(e1))
+        r = b.read()[0]
+        out[name] = {"ms": round(float(np.median(times)), 3), "exact": bool(r.verdict == ref.verdict and
+                                                                             r.accepting_left == ref.accepting_left),
+                     "sweeps": r.sweeps, "iterations": r.iterations}
+    print(json.dumps({"workload": WORKLOADS["hub"][0], "n": g.n, "m": g.m, "hub_degree": 100_000, **out}),
+          flush=True)
 
 
 def bench_serve(args):
@@ -621,6 +667,9 @@ def main():
         return
     if args.workload == "lasso":
         bench_lasso(args)
+        return
+    if args.workload == "hub":
+        bench_hub(args)
         return
     if args.workload == "onthefly":
         bench_onthefly(args)

@@ -273,12 +273,21 @@ int map_trim(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_
 /* One graph of a batch (device memory; see map_detect_batch). */
 typedef struct map_graph_desc {
   int32_t n;                  /* vertices, ids 1..n */
-  int32_t reserved;           /* 0 */
+  int32_t options;            /* 0 = defaults, else an or of the MAP_GRAPH_* bits below */
   int64_t m;                  /* edges */
   const int32_t *row_ptr;     /* device pull CSR from map_build_csr: int32[n+1] */
   const int32_t *col;         /* device int32[m] */
   const uint8_t *accepting0;  /* device uint8[n]: A_1, not modified */
 } map_graph_desc;
+
+/* map_graph_desc.options.  Low 16 bits: a row with more edges than this in a
+ * staged chunk of a streamed tile (512 edges) is folded by the whole wave
+ * instead of its own lane (0 = the default, 64).  MAP_GRAPH_SYNC_SWEEPS and
+ * MAP_GRAPH_STREAM apply MAP_FLAG_SYNC_SWEEPS / MAP_FLAG_STREAM to this graph
+ * alone.  None of them changes a result. */
+#define MAP_GRAPH_HUB_MASK 0xffff
+#define MAP_GRAPH_SYNC_SWEEPS 0x10000
+#define MAP_GRAPH_STREAM 0x20000
 
 /*
  * Bytes of device workspace for map_detect_batch over `count` graphs whose

@@ -54,6 +54,7 @@ constexpr uint32_t kAllFlags =
     MAP_FLAG_DENSE_ONLY | MAP_FLAG_NO_TRACE_DIGEST | MAP_FLAG_STREAM | MAP_FLAG_SYNC_SWEEPS | MAP_FLAG_PUSH |
     MAP_FLAG_EARLY | MAP_FLAG_NO_FILTER;
 constexpr uint32_t kAccBit = 0x80000000u;
+constexpr int kHubEdges = 64;  // stream tiles: default edges of a row in a staged chunk above which a wave folds it
 
 // Global-memory views of device pointers, for out-of-line functions where the
 // address space of a pointer loaded from an argument struct is not inferred.
@@ -166,6 +167,10 @@ __device__ __forceinline__ int wave_max_i32(int x) {
   x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x143, 0xC, 0xF, false));  // row_bcast:31
   return __builtin_amdgcn_readlane(x, 63);
 }
+
+// Max over the 64 lanes of values below 2^31 (map values and ids), result in
+// every lane: the same DPP row operations as wave_max_i32.
+__device__ __forceinline__ uint32_t wave_max_u31(uint32_t x) { return (uint32_t)wave_max_i32((int)x); }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
   for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
@@ -316,6 +321,7 @@ struct LoopArgs {
   uint32_t* accb;        // [words]
   int64_t words;         // 32-bit words per bitmap
   int32_t filt;          // 1: run the filtered stream kernel
+  int32_t hub;           // stream tiles: rows with more edges in a staged chunk are folded by the whole wave
 };
 
 // Row ownership: the rows are cut into one contiguous range per block and,
@@ -446,6 +452,34 @@ __device__ __forceinline__ uint32_t iter_tag(uint32_t tmask, uint32_t tshift, ui
   return (1u + (base + (uint32_t)k - 1u) % span) << tshift;
 }
 
+// Fold of one staged chunk of a stream tile into the maxima of the rows a lane
+// owns: a row with at most `hub` edges in the chunk is folded by its own lane;
+// each longer row is folded by the whole wave -- every lane takes every 64th of
+// its edges, then a DPP max gives the row's maximum to its lane.
+template <int kRows>
+__device__ __forceinline__ void fold_chunk(const uint32_t* val, const int32_t* lo, const int32_t* hi, int32_t c0,
+                                          int cnt, int hub, int lane, uint32_t* best) {
+#pragma unroll
+  for (int j = 0; j < kRows; ++j) {
+    const int b = max(lo[j] - c0, 0), e = min(hi[j] - c0, cnt);
+    const bool longrow = e - b > hub;
+    uint32_t m = best[j];
+    if (!longrow)
+      for (int k = b; k < e; ++k) m = max(m, val[k]);
+    unsigned long long lr = __ballot(longrow);
+    while (lr) {
+      const int src = __ffsll(lr) - 1;
+      lr &= lr - 1;
+      const int bb = __shfl(b, src, kWave), ee = __shfl(e, src, kWave);
+      uint32_t x = 0;
+      for (int k = bb + lane; k < ee; k += kWave) x = max(x, val[k]);
+      x = wave_max_u31(x);
+      if (lane == src) m = max(m, x);
+    }
+    best[j] = m;
+  }
+}
+
 // Value that successor w (0-based) sends along an edge: its map value, or its
 // own id if it is accepting and larger.  A word tagged with another iteration
 // has not been reset in this iteration yet and sends 0, a valid lower bound
@@ -467,7 +501,7 @@ __device__ __forceinline__ uint32_t sent_first(const uint8_t* acc, int32_t w) {
 // kFirst: the sweep that starts an iteration from map = 0 (successors send their
 // id if accepting, every row is written).  Otherwise a row is written only when
 // its value grows.  Returns nonzero (wave-uniform) if some row changed.
-template <bool kFirst>
+template <bool kFirst, bool kHub>
 __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int64_t r0, int64_t r1, TileLds& L, int lane,
                                uint32_t cur, uint32_t* acc_count) {
   const int nr = (int)(r1 - r0);
@@ -505,12 +539,16 @@ __device__ uint32_t sweep_tile(const LoopArgs& a, const uint8_t* acc, int64_t r0
       if (i < cnt) L.val[i] = x;
     }
     wave_lds_sync();
+    if (kHub) {
+      fold_chunk<kRowsPerLane>(L.val, lo, hi, c0, cnt, a.hub, lane, best);
+    } else {
 #pragma unroll
-    for (int j = 0; j < kRowsPerLane; ++j) {
-      int b = max(lo[j] - c0, 0), e = min(hi[j] - c0, cnt);
-      uint32_t m = best[j];
-      for (int k = b; k < e; ++k) m = max(m, L.val[k]);
-      best[j] = m;
+      for (int j = 0; j < kRowsPerLane; ++j) {
+        int b = max(lo[j] - c0, 0), e = min(hi[j] - c0, cnt);
+        uint32_t m = best[j];
+        for (int k = b; k < e; ++k) m = max(m, L.val[k]);
+        best[j] = m;
+      }
     }
     wave_lds_sync();
   }
@@ -782,10 +820,10 @@ __device__ uint32_t sweep_rows(const LoopArgs& a, const uint8_t* acc, const Wave
     const int64_t last = W.r0 + ((W.r1 - W.r0 - 1) / kTileRows) * kTileRows;
     if (W.ascending) {
       for (int64_t t0 = W.r0; t0 <= last; t0 += kTileRows)
-        ch |= sweep_tile<kFirst>(a, acc, t0, min(W.r1, t0 + kTileRows), g_lds.tile[wib], lane, cur, acc_count);
+        ch |= sweep_tile<kFirst, kBal>(a, acc, t0, min(W.r1, t0 + kTileRows), g_lds.tile[wib], lane, cur, acc_count);
     } else {
       for (int64_t t0 = last; t0 >= W.r0; t0 -= kTileRows)
-        ch |= sweep_tile<kFirst>(a, acc, t0, min(W.r1, t0 + kTileRows), g_lds.tile[wib], lane, cur, acc_count);
+        ch |= sweep_tile<kFirst, kBal>(a, acc, t0, min(W.r1, t0 + kTileRows), g_lds.tile[wib], lane, cur, acc_count);
     }
   }
   PH_MARK(kPhStream);
@@ -855,13 +893,7 @@ __device__ uint32_t sweep_tile_filt(const LoopArgs& a, const uint8_t* acc, int64
       if (i < cnt) L.val[i] = x;
     }
     wave_lds_sync();
-#pragma unroll
-    for (int j = 0; j < kRowsPerLane; ++j) {
-      int b = max(lo[j] - c0, 0), e = min(hi[j] - c0, cnt);
-      uint32_t m = best[j];
-      for (int k = b; k < e; ++k) m = max(m, L.val[k]);
-      best[j] = m;
-    }
+    fold_chunk<kRowsPerLane>(L.val, lo, hi, c0, cnt, a.hub, lane, best);
     wave_lds_sync();
   }
   uint32_t changed = 0, nacc = 0;
@@ -2109,7 +2141,7 @@ aborted:
 // Loop arguments of one graph solved by a gang: scratch holds the packed
 // values (4n bytes, 256-aligned) followed by the working accepting flags.
 __device__ LoopArgs gang_args(int32_t n, const int32_t* row_ptr, const int32_t* col, const uint8_t* acc0,
-                              char* scratch, map_result* result, uint32_t flags) {
+                              char* scratch, map_result* result, uint32_t flags, int32_t options) {
   LoopArgs a;
   a.n = n;
   a.ntiles = (int32_t)(((int64_t)n + kTileRows - 1) / kTileRows);
@@ -2138,6 +2170,11 @@ __device__ LoopArgs gang_args(int32_t n, const int32_t* row_ptr, const int32_t* 
   a.accb = nullptr;
   a.words = 0;
   a.filt = 0;
+  // Per-graph options of a batch (map_graph_desc.options): long-row threshold,
+  // barrier per sweep, streamed CSR.
+  a.hub = (options & MAP_GRAPH_HUB_MASK) ? (options & MAP_GRAPH_HUB_MASK) : kHubEdges;
+  if (options & MAP_GRAPH_SYNC_SWEEPS) a.sync_sweeps = 1;
+  if (options & MAP_GRAPH_STREAM) a.force_stream = 1;
   a.rcol = nullptr;
   a.front[0] = a.front[1] = nullptr;
   a.mark = nullptr;
@@ -2181,7 +2218,7 @@ __global__ void __launch_bounds__(kBlock) map_batch_kernel(BatchArgs ba) {
       continue;
     }
     char* base = ba.scratch + ba.scratch_off[gi];
-    const LoopArgs a = gang_args(d.n, d.row_ptr, d.col, d.accepting0, base, ba.results + gi, ba.flags);
+    const LoopArgs a = gang_args(d.n, d.row_ptr, d.col, d.accepting0, base, ba.results + gi, ba.flags, d.options);
     map_body_gang(a, ba.gctrl + gi, nb, rank);
   }
 }
@@ -2461,7 +2498,7 @@ __device__ __noinline__ void engine_job(const EngineArgs& ea, int slot, int rank
                         ej.host_edges ? reinterpret_cast<int32_t*>(stage + edge_bytes) : nullptr, g, nb, rank, &bad);
   }
   if (ok && bad == 0) {
-    const LoopArgs a = gang_args(j.n, j.row_ptr, j.col, j.accepting0, sc, res, ea.flags);
+    const LoopArgs a = gang_args(j.n, j.row_ptr, j.col, j.accepting0, sc, res, ea.flags, 0);
     map_body_gang(a, mcx, nb, rank);
   }
   // Leave the job: release this block's writes, then report (ranks > 0) or
@@ -3108,6 +3145,7 @@ static void loop_args(int32_t n, const int32_t* row_ptr, const int32_t* col, con
   a.chg = reinterpret_cast<uint32_t*>(w + L.chg);
   a.accb = reinterpret_cast<uint32_t*>(w + L.accb);
   a.words = L.words;
+  a.hub = kHubEdges;
 }
 
 static int loop_common(int32_t n, const int32_t* row_ptr, const int32_t* col, const uint8_t* acc, map_result* result,

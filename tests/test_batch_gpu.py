@@ -33,10 +33,11 @@ def graphs():
     return gs, refs
 
 
-def _check(mc, gs, refs, gang=None, flags=0, order=None):
+def _check(mc, gs, refs, gang=None, flags=0, order=None, options=None):
     order = list(range(len(gs))) if order is None else order
     csrs = [mc.build_csr(gs[i].n, gs[i].src, gs[i].dst, transposed=False) for i in order]
-    b = mc.Batch(csrs, [gs[i].acc for i in order], gang=gang, flags=flags)
+    opts = None if options is None else [options[i] for i in order]
+    b = mc.Batch(csrs, [gs[i].acc for i in order], gang=gang, flags=flags, options=opts)
     b.launch()
     res = b.read()
     for r, i in zip(res, order):
@@ -97,3 +98,26 @@ def test_batch_workspace_too_small_reports(mc, graphs):
     b.ws = torch.empty(mc.map_batch_workspace_bytes(3, 3), dtype=torch.uint8, device="cuda")
     b.launch()
     assert all(r.status == mc.MAP_ENOSPC for r in b.read())
+
+
+def _hub_graph():
+    """Out-hubs of 20,000 edges (many staged chunks) on a config-1 base."""
+    base = synth.config1(seed=11, n=50_000)
+    rng = np.random.default_rng(11)
+    hubs = [np.stack([np.full(20_000, h), rng.integers(1, base.n + 1, 20_000)], 1) for h in (5, 25_000)]
+    e = np.concatenate([np.stack([base.src, base.dst], 1)] + hubs).astype(np.int32)
+    return synth.Graph(n=base.n, src=e[:, 0].copy(), dst=e[:, 1].copy(), acc=base.acc, name="c1-hubs")
+
+
+@pytest.mark.parametrize("opt", ["hub1", "hub8", "hub-never", "sync", "stream", "stream+sync+hub16"])
+def test_batch_per_graph_options(mc, graphs, opt):
+    """Per-graph options (long-row threshold, barrier per sweep, streamed CSR)
+    on every other graph, the hub graph among them: every result exact."""
+    gs, refs = graphs
+    gs = gs + [_hub_graph()]
+    refs = refs + [oracle.map_detect(gs[-1], mode="desc")]
+    o = {"hub1": 1, "hub8": 8, "hub-never": mc.MAP_GRAPH_HUB_MASK, "sync": mc.MAP_GRAPH_SYNC_SWEEPS,
+         "stream": mc.MAP_GRAPH_STREAM,
+         "stream+sync+hub16": mc.MAP_GRAPH_STREAM | mc.MAP_GRAPH_SYNC_SWEEPS | 16}[opt]
+    options = [o if i % 2 == 0 or i == len(gs) - 1 else 0 for i in range(len(gs))]
+    _check(mc, gs, refs, gang=[1 if g.n < 20000 else 4 for g in gs], options=options)

@@ -220,6 +220,48 @@ def test_all_accepting_and_duplicates(mc):
     check_detect(mc, g)
 
 
+def hub_graph(n=200_000, seed=4):
+    """One out-hub of 100,000 edges spanning many staged chunks, one in-hub,
+    a chain, and 300 accepting vertices."""
+    rng = np.random.default_rng(seed)
+    hub_out = np.stack([np.full(100_000, 7), rng.integers(1, n + 1, 100_000)], 1)
+    hub_in = np.stack([rng.integers(1, n + 1, 50_000), np.full(50_000, 150_000)], 1)
+    chain = np.stack([np.arange(1000, 1500), np.arange(1001, 1501)], 1)
+    e = np.concatenate([hub_out, hub_in, chain]).astype(np.int32)
+    acc = np.zeros(n, np.uint8)
+    acc[rng.choice(n, 300, replace=False)] = 1
+    acc[150_000 - 1] = 1
+    return synth.Graph(n=n, src=e[:, 0].copy(), dst=e[:, 1].copy(), acc=acc, name="hubs")
+
+
+@pytest.mark.parametrize("flags", [0, 0x4, 0x4 | 0x40, 0x8], ids=["auto", "stream", "stream-async", "sync"])
+def test_hub_rows_all_modes(mc, flags):
+    """The hub graph in every sweep mode: streamed tiles fold the hub row with
+    the whole wave (filtered and asynchronous), barrier mode per lane."""
+    g = hub_graph()
+    csr = mc.build_csr(g.n, g.src, g.dst)
+    check_detect(mc, g, csr, flags=flags)
+    check_propagate_all(mc, g, csr, max_k=2, flags=flags)
+
+
+def test_hub_star_mix(mc):
+    """A config-3 style DAG with three out-hubs of 10^5 edges each and an
+    in-hub, streamed (every block streams at this size)."""
+    base = synth.config3(n=1 << 21)
+    rng = np.random.default_rng(9)
+    hubs = []
+    for h in (1 << 20, (1 << 21) - 5, 3 << 19):
+        hubs.append(np.stack([np.full(100_000, h), rng.integers(1, h, 100_000)], 1))
+    hubs.append(np.stack([rng.integers(1 << 20, 1 << 21, 30_000), np.full(30_000, 12345)], 1))
+    e = np.concatenate([np.stack([base.src, base.dst], 1)] + hubs).astype(np.int32)
+    acc = base.acc.copy()
+    acc[[12345 - 1, 999 - 1]] = 1
+    g = synth.Graph(n=base.n, src=e[:, 0].copy(), dst=e[:, 1].copy(), acc=acc, name="hub-star-mix")
+    csr = mc.build_csr(g.n, g.src, g.dst)
+    check_detect(mc, g, csr)
+    check_detect(mc, g, csr, flags=mc.MAP_FLAG_NO_FILTER)
+
+
 def test_hub_rows(mc):
     # one out-hub spanning many LDS chunks, one in-hub, plus a chain
     n = 200_000
