@@ -169,7 +169,7 @@ def batch_run(args, count, capture=True):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.perf_counter()
-    csrs, accs, ns, ms = [], [], [], []
+    csrs, accs, ns, ms, dmaxs = [], [], [], [], []
     ws = None
     for i in range(count):
         g = synth.config4(i)
@@ -179,6 +179,7 @@ def batch_run(args, count, capture=True):
         accs.append(torch.from_numpy(g.acc).to(dev))
         ns.append(g.n)
         ms.append(g.m)
+        dmaxs.append(int(np.bincount(g.src).max()) if g.m else 0)
     torch.cuda.synchronize()
     print(f"[bench] c4: {count} graphs, sum n={sum(ns)} sum m={sum(ms)}, generated+uploaded in "
           f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -187,14 +188,17 @@ def batch_run(args, count, capture=True):
     o_accs = [accs[i] for i in order]
     o_ns = [ns[i] for i in order]
     o_ms = [ms[i] for i in order]
+    o_dmax = [dmaxs[i] for i in order]
 
-    def make(gang):
-        return mc.Batch(o_csrs, o_accs, gang=gang, device=dev)
+    def make(gang, options=None):
+        return mc.Batch(o_csrs, o_accs, gang=gang, device=dev, options=options)
 
-    policy, timings = autotune.tune(make, o_ns, o_ms, torch.cuda.get_device_name(0), use_cache=False,
-                                    log=lambda x: print(x, file=sys.stderr, flush=True))
+    choice, timings = autotune.tune_knobs(make, o_ns, o_ms, o_dmax, torch.cuda.get_device_name(0), use_cache=False,
+                                          log=lambda x: print(x, file=sys.stderr, flush=True))
+    policy = choice["gang"]
     gang = autotune.gang_sizes(o_ns, o_ms, policy)
-    b = make(gang)
+    options = autotune.graph_options(choice["options"], gang, o_ns, o_dmax)
+    b = make(gang, options)
     for _ in range(args.warmup):
         b.launch()
     torch.cuda.synchronize()
@@ -221,10 +225,10 @@ def batch_run(args, count, capture=True):
     t_plain = time.perf_counter() - t
     plain = [mc.Result.from_tensor(results_plain[j]) for j in range(count)]
 
-    # the one-workgroup-per-graph launch captured in a HIP graph, replayed
+    # the tuned launch captured in a HIP graph, replayed
     t_graph = None
     graph_ok = None
-    bg = make(None) if capture else None
+    bg = make(gang, options) if capture else None
     if bg is None:
         reps = 0
     else:
@@ -264,7 +268,7 @@ def batch_run(args, count, capture=True):
                    f"the first {count} of the 4,096 config-4 graphs", "key": "c4", "graphs": count,
                    "sum_n": int(sum(ns)),
                    "sum_m": int(sum(ms)), "parallelism": "single GPU", "order": "largest first",
-                   "gang_policy": autotune.policy_name(policy)},
+                   "gang_policy": autotune.policy_name(policy), "option_rule": choice["options"]},
         "plain_graphs_per_s": round(count / t_plain, 2), "plain_ms": round(t_plain * 1e3, 3),
         "speedup_vs_plain": round(t_plain / t_batch, 3),
         "hipgraph_graphs_per_s": round(count / t_graph, 2) if t_graph else None,
