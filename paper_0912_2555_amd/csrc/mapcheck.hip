@@ -373,6 +373,11 @@ __shared__ BlockLds g_lds;
 // MAP_FLAG_EARLY: the largest id of a row of this block whose value equals
 // its own id (0: none), found by a scan of the block's rows after each sweep.
 __shared__ uint32_t g_early;
+// Resident asynchronous bodies: where each wave's edges to other blocks' rows
+// start in the staged slice, and the prefix sums of their counts, so that the
+// block's remote edges can be shared evenly over its waves.
+__shared__ int32_t g_rseg[kWavesPerBlock];
+__shared__ int32_t g_rpre[kWavesPerBlock + 1];
 
 #ifdef MAPCHECK_PHASES
 // Phase clocks of the loop kernel, in a build made only to measure where the
@@ -607,6 +612,52 @@ __device__ __forceinline__ void gather_range(const uint8_t* acc, int32_t e0, int
   }
 }
 
+// Resident mode, kBal: the pass over the block's edges to other blocks' rows,
+// shared evenly over the block's waves (the waves' staged lists taken as one
+// list of g_rpre[16] edges), each value folded with an LDS atomic max into the
+// maxima of its row's wave.  Every wave must have cleared its maxima before
+// (block barrier), and the rows are updated after another block barrier.
+template <int kSrc>
+__device__ __forceinline__ void gather_block(const uint8_t* acc, uint32_t* best_all, const LoopArgs& a, int wib,
+                                             int lane, uint32_t cur) {
+  ResLds& R = g_lds.res;
+  g_u32* pv = (g_u32*)a.pv;
+  const uint32_t n = (uint32_t)a.n, vmask = a.val_mask, tmask = a.tag_mask;
+  const int32_t total = g_rpre[kWavesPerBlock];
+  const int32_t share = (total + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int32_t lo = min(total, wib * share), hi = min(total, lo + share);
+  for (int32_t g0 = lo; g0 < hi; g0 += kWave * kGatherBatch) {
+    uint32_t e[kGatherBatch];
+    int32_t seg[kGatherBatch];
+    int w = 0;  // the list a lane's next edge lies in (its edges increase)
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u) {
+      const int32_t gi = g0 + lane + u * kWave;
+      e[u] = 0xffffffffu;
+      seg[u] = 0;
+      if (gi < hi) {
+        while (gi >= g_rpre[w + 1]) ++w;
+        e[u] = R.e[g_rseg[w] + (gi - g_rpre[w])];
+        seg[u] = w;
+      }
+    }
+    uint32_t x[kGatherBatch];
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u) {
+      x[u] = 0;
+      const uint32_t wv = e[u] >> 8;
+      if (e[u] != 0xffffffffu && wv < n) {
+        if (kSrc == 0) x[u] = sent_first(acc, (int32_t)wv);
+        else x[u] = sent_word(pv[wv], (int32_t)wv, cur, vmask, tmask);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherBatch; ++u) {
+      if (x[u] != 0) atomicMax(&best_all[seg[u] * kResWaveRows + (e[u] & 0xffu)], x[u]);
+    }
+  }
+}
+
 // Rows of the wave in the order values travel: a row takes values from its
 // successors, so when the block's edges mostly point to higher rows values
 // flow downwards and the rows go from high to low.
@@ -722,8 +773,13 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, const 
   const int32_t nrow = (int32_t)(W.r1 - W.r0), r0 = (int32_t)(W.r0 - W.rb0);
 #pragma unroll
   for (int j = 0; j < kResRowsPerLane; ++j) best[lane + j * kWave] = 0;
-  wave_lds_sync();
-  gather_range<kFirst ? 0 : 1>(acc, W.we0, W.wr, best, a, lane, cur);
+  if (kBal) {
+    __syncthreads();  // every wave's maxima cleared before any wave folds into them
+    gather_block<kFirst ? 0 : 1>(acc, &R.best[0][0], a, wib, lane, cur);
+  } else {
+    wave_lds_sync();
+    gather_range<kFirst ? 0 : 1>(acc, W.we0, W.wr, best, a, lane, cur);
+  }
   if (kFirst && kBal) {
     // In-block successors send their id if accepting: folded like the remote
     // edges, shared evenly over the lanes.
@@ -733,7 +789,8 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, const 
       if (x) atomicMax(&best[in_row(e)], x);
     }
   }
-  wave_lds_sync();
+  if (kBal) __syncthreads();  // every wave's folds into these maxima are done
+  else wave_lds_sync();
   uint32_t changed = 0, nacc = 0;
 #pragma unroll
   for (int j = 0; j < kResRowsPerLane; ++j) {
@@ -1144,6 +1201,18 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
       sort_gather_batches(W.we0, W.wr, lane);
     }
     __syncthreads();
+    if (kBal && W.resident) {  // block-uniform
+      if (lane == 0) {
+        g_rseg[wib] = W.we0;
+        g_rpre[wib + 1] = W.wr - W.we0;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        g_rpre[0] = 0;
+        for (int i = 1; i <= kWavesPerBlock; ++i) g_rpre[i] += g_rpre[i - 1];
+      }
+      __syncthreads();
+    }
   }
 
   Grid<C> g;
