@@ -128,8 +128,10 @@ size_t map_workspace_bytes(int32_t n, int64_t m, uint32_t flags);
  *              frontier sweeps (MAP_FLAG_PUSH).
  *   status     device int32 out: MAP_OK, or MAP_ERANGE_DEV if an id lies
  *              outside 1..n (the CSR contents are then unspecified).
- * Duplicate edges and self-loops are kept.  Column order within a row is
- * unspecified (it does not affect any result).
+ * Duplicate edges and self-loops are kept.  The columns of each row follow
+ * the order of their edges in src/dst (a stable counting sort by key), so the
+ * CSR is the same on every run.  The workspace holds a per-edge scratch of 4m
+ * bytes beside the per-vertex arrays.
  */
 int map_build_csr(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t *row_ptr,
                   int32_t *col, int32_t *rrow_ptr, int32_t *rcol, int32_t *status, void *ws,
@@ -216,8 +218,12 @@ typedef struct map_lasso_result {
  * vertex to the witness and a shortest cycle in G through the witness.  Both
  * are found by breadth-first search over the successor rows of the pull CSR
  * that map_detect uses, in one cooperative launch (a grid barrier per round).
- * The two lengths are unique; the vertices are one valid choice, which may
- * differ from run to run when several shortest paths exist.
+ * The two lengths are unique.  Where several shortest paths exist, the one
+ * returned is fixed by the edge set alone (not by column order or schedule):
+ * walking back from the end of the stem and of the cycle, each step goes to
+ * the smallest vertex one breadth-first level closer to the start that has an
+ * edge to the current one; of all shortest paths, the one whose vertices read
+ * backwards are lexicographically smallest.
  *   row_ptr, col  device pull CSR of G from map_build_csr (row v = successors).
  *   witness       1..n, typically map_result.witness of a found cycle.
  *   init          1..n: the stem starts there; 0 (or == witness): no stem.
@@ -321,7 +327,8 @@ int map_detect_batch(int32_t count, const map_graph_desc *graphs, const int32_t 
  * posts jobs into fine-grained host memory and the kernel's workgroups pick
  * them up as they free up, so a job submitted while others run starts on the
  * workgroups the earlier jobs release, with no new launch.  Each job is an edge
- * list: its gang of workgroups builds the pull CSR (as map_build_csr) and runs
+ * list: its gang of workgroups builds the pull CSR (as map_build_csr, up to the
+ * order of the columns inside a row) and runs
  * the MAP loop on it (as map_detect, without trace, accepting_out or iteration
  * cap); the result is written to host memory.  The edge list and flags may stay
  * in pinned host memory (hipHostMalloc, torch pin_memory): the engine reads
@@ -341,7 +348,7 @@ typedef struct map_job {
   const int32_t *src;         /* int32[m]: edge src[i] -> dst[i], ids 1..n (device or pinned host) */
   const int32_t *dst;         /* int32[m] (device or pinned host) */
   int32_t *row_ptr;           /* device int32[n+1] out: pull CSR (as map_build_csr) */
-  int32_t *col;               /* device int32[m] out */
+  int32_t *col;               /* device int32[m] out (column order inside a row unspecified) */
   const uint8_t *accepting0;  /* uint8[n]: A_1, not modified (device or pinned host) */
   void *scratch;              /* device, map_job_scratch_bytes(n, m) bytes, 256-byte aligned */
   uint64_t tag;               /* free for the caller; not read by the engine */

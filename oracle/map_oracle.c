@@ -491,8 +491,12 @@ int oracle_ndfs(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, co
  * generation as missing from the tool, Section 5): a lasso made of a shortest
  * path from an initial vertex `init` to the witness w and a shortest cycle
  * through w, both along edges of G, found by breadth-first search over
- * successors.  Their lengths are unique; the vertices are one valid choice
- * (the first discovery in edge-list order).
+ * successors.  Their lengths are unique.  The paper fixes no choice among
+ * several shortest paths; this one takes, walking back from the end, the
+ * smallest vertex of each breadth-first level that has an edge to the vertex
+ * after it: of all shortest paths, the one whose vertices read backwards are
+ * lexicographically smallest (so the path depends on the edge set alone, not
+ * on the order of the edge list).
  *
  * path receives init = s_0, ..., s_S = w, c_1, ..., c_L = w (S + L + 1 ids);
  * without an initial vertex (init == 0) or with init == w, S = 0.
@@ -503,30 +507,36 @@ int oracle_ndfs(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, co
 #define OR_ENOPATH -8
 #define OR_ENOSPC -9
 
-/* Breadth-first search from `from` until an edge enters `to`; parent[v] is
- * the vertex v was first reached from (0: not reached).  `from` itself is
- * not marked, so from == to finds a shortest cycle.  Returns the number of
- * edges of a shortest path of >= 1 edge, or -1; *last is the vertex whose
- * edge entered `to`. */
+static int cmp_i32(const void *a, const void *b) {
+    const int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Breadth-first search from `from`, one level at a time, until an edge enters
+ * `to`.  Each level is expanded in increasing vertex order, so parent[v] is
+ * the smallest vertex of the level before v's with an edge to v (0: not
+ * reached) and *last the smallest vertex of the final level with an edge to
+ * `to`.  `from` itself is not marked, so from == to finds a shortest cycle.
+ * Returns the number of edges of a shortest path of >= 1 edge, or -1. */
 static int32_t bfs_to(const adj_t *s, int32_t from, int32_t to, int32_t *parent, int32_t *queue,
                       int32_t *last) {
     memset(parent, 0, ((size_t)s->n + 1) * sizeof(int32_t));
     int64_t head = 0, tail = 0;
     queue[tail++] = from;
-    int32_t dist_head = 0;
-    /* level boundaries: queue[level_end] starts the next level */
-    int64_t level_end = tail;
-    while (head < tail) {
-        int32_t u = queue[head++];
-        for (int64_t j = s->off[u]; j < s->off[u + 1]; ++j) {
-            int32_t v = s->nb[j];
-            if (v == to) { *last = u; return dist_head + 1; }
-            if (v != from && parent[v] == 0) {
-                parent[v] = u;
-                queue[tail++] = v;
+    for (int32_t dist = 0; head < tail; ++dist) {
+        const int64_t level_end = tail;
+        qsort(queue + head, (size_t)(level_end - head), sizeof(int32_t), cmp_i32);
+        for (; head < level_end; ++head) {
+            const int32_t u = queue[head];
+            for (int64_t j = s->off[u]; j < s->off[u + 1]; ++j) {
+                const int32_t v = s->nb[j];
+                if (v == to) { *last = u; return dist + 1; }
+                if (v != from && parent[v] == 0) {
+                    parent[v] = u;
+                    queue[tail++] = v;
+                }
             }
         }
-        if (head == level_end) { dist_head++; level_end = tail; }
     }
     return -1;
 }

@@ -110,7 +110,7 @@ struct alignas(256) CtrlT {
   alignas(128) uint32_t done;
   uint32_t pad2[31];
   alignas(128) uint32_t fcount[2];  // push and lasso: entries appended to frontier 0 / 1
-  uint32_t hit;                     // lasso: 1 + the vertex whose edge reached the target
+  uint32_t hit;                     // lasso: smallest vertex whose edge reached the target, or kNoHit
   uint32_t bad;                     // lasso and trim: an edge endpoint outside 0..n-1 was read
   unsigned long long scanned;       // lasso: edges examined
   uint32_t kept;                    // trim: vertices kept
@@ -1783,7 +1783,8 @@ struct LassoArgs {
   int32_t* path;           // ids out
   int32_t cap;
   map_lasso_result* result;
-  int32_t* parent;         // [n]: 0 unreached, 1 + the vertex it was reached from, -1 the start
+  uint64_t* parent;        // [n]: level << 32 | (1 + the vertex it was reached from); the start
+                           // level 0 with low word -1; unreached kUnreached
   int32_t* front[2];       // frontiers [n]
   Ctrl* ctrl;
 };
@@ -1808,6 +1809,8 @@ __device__ uint32_t lasso_block_sum(uint32_t x) {
 // up to 64 * kExpandPerLane edges together, instead of one edge per lane per
 // step, and appends what it claimed with one counter update per chunk.
 constexpr int kExpandPerLane = 4;
+constexpr uint64_t kUnreached = ~0ull;    // lasso parent word of a vertex not reached
+constexpr uint32_t kNoHit = 0xffffffffu;  // lasso: no edge has entered the target yet
 
 // Lane of this wave whose slice of the combined list holds slot q: the last
 // lane whose first slot is <= q (binary search over the lanes with shuffles;
@@ -1847,12 +1850,17 @@ __device__ __forceinline__ uint32_t frontier_append_n(int32_t* F, uint32_t* cnt,
 }
 
 // Breadth-first search from `from` until an edge enters `to`, run by every
-// thread of the grid.  The start is marked reached (parent -1) but an edge
-// into `to` is taken before that mark is looked at, so from == to finds a
-// shortest cycle.  Each round expands one frontier: a wave takes 64 frontier
-// vertices, a lane walks its vertex's successors, an unreached successor is
-// claimed with a compare-and-swap on its parent word and appended to the next
-// frontier; an edge into `to` records its source in c->hit.  A grid barrier
+// thread of the grid.  The start is marked reached (level 0) but an edge into
+// `to` is taken before that mark is looked at, so from == to finds a shortest
+// cycle.  Each round expands one frontier: a wave takes 64 frontier vertices
+// and a lane walks its vertex's successors.  A successor not reached in an
+// earlier round takes, by an atomic minimum on its 64-bit parent word (round
+// in the high half), the smallest frontier vertex with an edge to it; the
+// lane whose minimum found the word unreached appends it to the next
+// frontier.  An edge into `to` takes the minimum of its source into c->hit.
+// The parents, the last vertex and so the path therefore depend only on the
+// edge set, not on the column order or the schedule: walking back from `to`,
+// each step goes to the smallest vertex of the level before.  A grid barrier
 // ends each round and carries the size of the next frontier.  Returns the
 // length of a shortest path of >= 1 edge, 0 if `to` is not reached, -1 if a
 // barrier wait gave up (the launch must stop); *last (every block) is the
@@ -1863,19 +1871,19 @@ __device__ int32_t lasso_bfs(const LassoArgs& a, Grid<Ctrl>& g, int32_t from, in
   const int lane = threadIdx.x & (kWave - 1), wib = threadIdx.x / kWave;
   const int64_t gw = (int64_t)g.rank * kWavesPerBlock + wib, nw = (int64_t)g.nblocks * kWavesPerBlock;
   for (int64_t v = (int64_t)g.rank * kBlock + threadIdx.x; v < a.n; v += (int64_t)g.nblocks * kBlock)
-    a.parent[v] = 0;
+    a.parent[v] = kUnreached;
   if (g.rank == 0 && threadIdx.x == 0) {
-    st_agent(&c->hit, 0u);
+    st_agent(&c->hit, kNoHit);
     st_agent(&c->fcount[0], 0u);
     st_agent(&c->fcount[1], 0u);
   }
   if (!grid_sync(g, 0, nullptr)) return -1;
   if (g.rank == 0 && threadIdx.x == 0) {
     a.front[0][0] = from;
-    a.parent[from] = -1;
+    a.parent[from] = 0xffffffffull;  // level 0, low word -1
   }
   if (!grid_sync(g, 0, nullptr)) return -1;
-  uint32_t* parent = reinterpret_cast<uint32_t*>(a.parent);
+  uint64_t* parent = a.parent;
   uint32_t size = 1;
   int fc = 0;
   for (int32_t level = 1;; ++level) {
@@ -1921,34 +1929,31 @@ __device__ int32_t lasso_bfs(const LassoArgs& a, Grid<Ctrl>& g, int32_t from, in
           ok[s] = q < total;
           v[s] = ok[s] ? a.col[ko + (int32_t)(q - fo)] : 0;
         }
-        // Plain parent reads: a parent word only goes from 0 to nonzero during
-        // a search (the clear precedes a barrier), so nonzero is final; the
-        // compare-and-swap decides the claim.
+        // Plain reads of the round in a parent word: words set in an earlier
+        // round are final (they precede a barrier) and are skipped; an
+        // unreached word or one of this round takes the atomic minimum.
 #pragma unroll
         for (int s = 0; s < kExpandPerLane; ++s) {
-          pw[s] = 1u;
+          pw[s] = 0u;
           if (!ok[s]) continue;
           ++*scanned;
           if ((uint32_t)v[s] >= (uint32_t)a.n) {
             st_agent(&c->bad, 1u);
             ok[s] = false;
           } else if (v[s] == to) {
-            uint32_t zero = 0;
-            __hip_atomic_compare_exchange_strong(&c->hit, &zero, (uint32_t)src[s] + 1u, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_min(&c->hit, (uint32_t)src[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             ok[s] = false;
           } else {
-            pw[s] = parent[v[s]];
+            pw[s] = (uint32_t)(parent[v[s]] >> 32);
           }
         }
 #pragma unroll
         for (int s = 0; s < kExpandPerLane; ++s) {
           take[s] = false;
-          if (ok[s] && pw[s] == 0u) {
-            uint32_t zero = 0;
-            take[s] = __hip_atomic_compare_exchange_strong(&parent[v[s]], &zero, (uint32_t)src[s] + 1u,
-                                                           __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT);
+          if (ok[s] && pw[s] >= (uint32_t)level) {
+            const uint64_t claim = ((uint64_t)(uint32_t)level << 32) | (uint32_t)(src[s] + 1);
+            take[s] = __hip_atomic_fetch_min(&parent[v[s]], claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                      kUnreached;
           }
         }
         napp += frontier_append_n<kExpandPerLane>(Fn, cn, take, v, lane);
@@ -1959,8 +1964,8 @@ __device__ int32_t lasso_bfs(const LassoArgs& a, Grid<Ctrl>& g, int32_t from, in
     *levels += 1;
     if (ld_agent(&c->bad)) return 0;
     const uint32_t h = ld_agent(&c->hit);
-    if (h) {
-      *last = (int32_t)h - 1;
+    if (h != kNoHit) {
+      *last = (int32_t)h;
       return level;
     }
     if (tot == 0) return 0;
@@ -1976,7 +1981,7 @@ __device__ bool lasso_walk(const LassoArgs& a, int32_t x, int32_t hi, int32_t lo
   for (int32_t i = hi; i >= lo; --i) {
     if ((uint32_t)x >= (uint32_t)a.n) return false;
     a.path[i] = x + 1;
-    const int32_t p = (int32_t)ld_agent((const uint32_t*)&a.parent[x]);
+    const int32_t p = (int32_t)(uint32_t)__hip_atomic_load(&a.parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (i == lo) return p == root + 1 || (p == -1 && x == root);
     if (p <= 0) return false;
     x = p - 1;
@@ -2855,10 +2860,13 @@ __global__ void copy_i32(int32_t* dst, const int32_t* src, int64_t count) {
     dst[i] = src[i];
 }
 
-// col[cursor[key-1]++] = other-1 for every in-range edge; a run of equal keys
-// reserves its slots with one atomic and fills them in edge order.
+// col[cursor[key-1]++] = other-1 and ids[same slot] = edge index for every
+// in-range edge; a run of equal keys reserves its slots with one atomic and
+// fills them in edge order.  The order of the runs inside a row depends on the
+// schedule; the csr_order_* kernels then put every row whose edge indices are
+// out of order in edge order.
 __global__ void csr_scatter(int32_t n, int64_t m, const int32_t* __restrict__ key, const int32_t* __restrict__ other,
-                            int32_t* cursor, int32_t* col) {
+                            int32_t* cursor, int32_t* col, int32_t* ids) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t w0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); w0 < m; w0 += stride) {
@@ -2874,7 +2882,215 @@ __global__ void csr_scatter(int32_t n, int64_t m, const int32_t* __restrict__ ke
     int32_t pos = 0;
     if (r.head) pos = atomicAdd(&cursor[k - 1], r.len);
     pos = __shfl(pos, r.first, kWave) + (lane - r.first);
-    if (valid) col[pos] = o - 1;
+    if (valid) {
+      col[pos] = o - 1;
+      ids[pos] = (int32_t)i;
+    }
+  }
+}
+
+// Putting each row in edge order: rows of at most kOrderShort edges by one
+// lane, rows of at most 64 by one wave, longer rows by one workgroup.  A row
+// whose edge indices already ascend (the usual case for edge lists grouped by
+// source, where one wave's run fills most rows) is only read.
+constexpr int kOrderShort = 16;
+constexpr int kOrderChunk = 4096;   // long rows: entries sorted in LDS at a time
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderLongGrid = 256;
+constexpr int kOrderMidGrid = 1024;
+
+// Appends `val` for every lane with `take` to list[count...] (from the back,
+// list[back - 1 - index], when back > 0).  All 64 lanes must call it.
+__device__ void wave_list_append(bool take, int32_t val, int32_t* list, int32_t* count, int64_t back, int lane) {
+  const unsigned long long mask = __ballot(take);
+  if (!mask) return;
+  const int leader = __builtin_ctzll(mask);
+  int32_t base = 0;
+  if (lane == leader) base = atomicAdd(count, __popcll(mask));
+  base = __shfl(base, leader, kWave);
+  const int64_t idx = base + __popcll(mask & ((1ull << lane) - 1ull));
+  if (take) list[back > 0 ? back - 1 - idx : idx] = val;
+}
+
+// A row of 2..W edges in one lane: its edge indices are loaded together (no
+// branch between the loads, so their latencies overlap) and, unless they
+// ascend, each column is written at the rank of its edge index in the row.
+template <int W>
+__device__ __forceinline__ void order_short_row(int32_t b, int32_t d, int32_t* col, const int32_t* __restrict__ ids) {
+  int32_t e[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) e[k] = k < d ? ids[b + k] : INT32_MAX;
+  bool sorted = true;
+#pragma unroll
+  for (int k = 1; k < W; ++k) sorted = sorted && e[k - 1] < e[k];
+  if (sorted) return;
+  int32_t o[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) o[k] = k < d ? col[b + k] : 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    int rank = 0;
+#pragma unroll
+    for (int q = 0; q < W; ++q) rank += e[q] < e[k] ? 1 : 0;
+    if (k < d) col[b + rank] = o[k];
+  }
+}
+
+// One lane per row of 2..kOrderShort edges (order_short_row, at the width of
+// the wave's longest such row).  Rows of kOrderShort+1..64 edges go to the
+// front of `lists` (count counts[0]), longer ones to its back (n entries,
+// count counts[1]); both counts start at zero.  Waves step over the rows in
+// grid strides (the launch grid is capped).
+__global__ void csr_order_rows(int32_t n, const int32_t* __restrict__ row_ptr, int32_t* col,
+                               const int32_t* __restrict__ ids, int32_t* lists, int32_t* counts) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); r0 < n; r0 += stride) {
+    const int64_t r = r0 + lane;
+    int32_t b = 0, d = 0;
+    if (r < n) {
+      b = row_ptr[r];
+      d = row_ptr[r + 1] - b;
+    }
+    wave_list_append(d > kOrderShort && d <= kWave, (int32_t)r, lists, &counts[0], 0, lane);
+    wave_list_append(d > kWave, (int32_t)r, lists, &counts[1], n, lane);
+    const bool mine = d >= 2 && d <= kOrderShort;
+    int dm = mine ? d : 0;  // longest short row of the wave
+    for (int off = kWave / 2; off > 0; off >>= 1) dm = max(dm, __shfl_xor(dm, off, kWave));
+    if (!mine) continue;
+    if (dm <= 4)
+      order_short_row<4>(b, d, col, ids);
+    else if (dm <= 8)
+      order_short_row<8>(b, d, col, ids);
+    else
+      order_short_row<kOrderShort>(b, d, col, ids);
+  }
+}
+
+// One wave per listed row of kOrderShort+1..64 edges: lane l holds entry l;
+// unless the edge indices ascend, each lane counts the lanes with a smaller
+// one and writes its column there.
+__global__ void csr_order_mid(const int32_t* __restrict__ row_ptr, int32_t* col, const int32_t* __restrict__ ids,
+                              const int32_t* __restrict__ lists, const int32_t* __restrict__ counts) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+  const int32_t cnt = counts[0];
+  for (int64_t li = gw; li < cnt; li += nw) {
+    const int32_t r = lists[li];
+    const int32_t b = row_ptr[r], d = row_ptr[r + 1] - b;
+    const int32_t e = lane < d ? ids[b + lane] : INT32_MAX;
+    const int32_t prev = __shfl_up(e, 1, kWave);
+    if (!__ballot(lane > 0 && lane < d && prev > e)) continue;
+    const int32_t o = lane < d ? col[b + lane] : 0;
+    int rank = 0;
+#pragma unroll
+    for (int q = 0; q < kWave; ++q) rank += __builtin_amdgcn_readlane(e, q) < e ? 1 : 0;
+    if (lane < d) col[b + rank] = o;  // every lane's read precedes (the ranks depend on all of them)
+  }
+}
+
+// Compare-exchange step of an ascending bitonic sort over se/so[0, S): pairs
+// (i, i ^ (k - 1)) on the first step of merge size k, else (i, i + j); the
+// smaller edge index goes to the lower position.
+__device__ void order_lds_step(int32_t* se, int32_t* so, int S, int k, int j, bool first) {
+  for (int t = threadIdx.x; t < S / 2; t += blockDim.x) {
+    const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+    const int p = first ? (i ^ (k - 1)) : (i + j);
+    const int32_t x = se[i], y = se[p];
+    if (x > y) {
+      se[i] = y;
+      se[p] = x;
+      const int32_t z = so[i];
+      so[i] = so[p];
+      so[p] = z;
+    }
+  }
+  __syncthreads();
+}
+
+// The same step over a whole row in global memory (E edge indices, O columns,
+// d entries, P the power of two the network spans).  Positions d and beyond
+// stand for +infinity: a pair that reaches one never exchanges.
+__device__ void order_global_step(int32_t* E, int32_t* O, int64_t d, int64_t P, int64_t k, int64_t j, bool first) {
+  for (int64_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+    const int64_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+    const int64_t p = first ? (i ^ (k - 1)) : (i + j);
+    if (p >= d) continue;
+    const int32_t x = E[i], y = E[p];
+    if (x > y) {
+      E[i] = y;
+      E[p] = x;
+      const int32_t z = O[i];
+      O[i] = O[p];
+      O[p] = z;
+    }
+  }
+  __syncthreads();
+}
+
+// Entries [c0, c0 + S) of a row through LDS: either a whole bitonic sort of
+// the chunk (k == 0) or the steps j = S/2 .. 1 of merge size k.  The entries
+// below d go back to E and O, or only to O on the chunk's last pass.
+__device__ void order_lds_chunk(int32_t* se, int32_t* so, int32_t* E, int32_t* O, int64_t d, int64_t c0, int S,
+                                int64_t k, bool last) {
+  for (int i = threadIdx.x; i < S; i += blockDim.x) {
+    const int64_t g = c0 + i;
+    se[i] = g < d ? E[g] : INT32_MAX;
+    so[i] = g < d ? O[g] : 0;
+  }
+  __syncthreads();
+  if (k == 0) {
+    for (int kk = 2; kk <= S; kk <<= 1) {
+      order_lds_step(se, so, S, kk, kk >> 1, true);
+      for (int j = kk >> 2; j > 0; j >>= 1) order_lds_step(se, so, S, kk, j, false);
+    }
+  } else {
+    for (int j = S >> 1; j > 0; j >>= 1) order_lds_step(se, so, S, 0, j, false);
+  }
+  for (int i = threadIdx.x; i < S; i += blockDim.x) {
+    const int64_t g = c0 + i;
+    if (g >= d) break;
+    if (!last) E[g] = se[i];
+    O[g] = so[i];
+  }
+  __syncthreads();
+}
+
+// One workgroup per listed row of more than 64 edges (from the back of
+// `lists`, count counts[1]) whose edge indices do not ascend: an ascending
+// bitonic sort of (edge index, column) pairs, in LDS for rows of up to
+// kOrderChunk entries, else chunks sorted in LDS and merged by steps over the
+// row in global memory (the row's edge indices are scratch).
+__global__ void __launch_bounds__(kOrderThreads)
+    csr_order_long(int32_t n, const int32_t* __restrict__ row_ptr, int32_t* col, int32_t* ids,
+                   const int32_t* __restrict__ lists, const int32_t* __restrict__ counts) {
+  __shared__ int32_t se[kOrderChunk];
+  __shared__ int32_t so[kOrderChunk];
+  const int32_t cnt = counts[1];
+  for (int32_t li = blockIdx.x; li < cnt; li += gridDim.x) {
+    const int32_t r = lists[(int64_t)n - 1 - li];
+    const int64_t b = row_ptr[r];
+    const int64_t d = (int64_t)row_ptr[r + 1] - b;
+    int32_t* E = ids + b;
+    int32_t* O = col + b;
+    int descents = 0;
+    for (int64_t i = 1 + threadIdx.x; i < d; i += blockDim.x) descents |= E[i - 1] > E[i] ? 1 : 0;
+    if (!__syncthreads_or(descents)) continue;
+    if (d <= kOrderChunk) {
+      int S = 2 * kWave;
+      while (S < d) S <<= 1;
+      order_lds_chunk(se, so, E, O, d, 0, S, 0, true);
+      continue;
+    }
+    int64_t P = kOrderChunk;
+    while (P < d) P <<= 1;
+    for (int64_t c0 = 0; c0 < d; c0 += kOrderChunk) order_lds_chunk(se, so, E, O, d, c0, kOrderChunk, 0, false);
+    for (int64_t k = 2 * (int64_t)kOrderChunk; k <= P; k <<= 1) {
+      order_global_step(E, O, d, P, k, k >> 1, true);
+      for (int64_t j = k >> 2; j >= kOrderChunk; j >>= 1) order_global_step(E, O, d, P, k, j, false);
+      for (int64_t c0 = 0; c0 < d; c0 += kOrderChunk) order_lds_chunk(se, so, E, O, d, c0, kOrderChunk, k, k == P);
+    }
   }
 }
 
@@ -2885,11 +3101,12 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 bool sizes_ok(int32_t n, int64_t m) { return n >= 1 && n <= 0x7ffffffe && m >= 0 && m <= 0x7fffffff; }
 
 struct Layout {
-  size_t ctrl, pv, accw, front0, front1, mark, aux, chg, accb, cursor, sums, total;
+  size_t ctrl, pv, accw, front0, front1, mark, aux, chg, accb, parent, cursor, sums, counts, ids, total;
   int64_t words;  // 32-bit words of one vertex bitmap
 };
 
-Layout layout(int32_t n) {
+// m > 0 adds the CSR build's per-edge scratch.
+Layout layout(int32_t n, int64_t m = 0) {
   Layout L;
   size_t off = 0;
   L.ctrl = off;
@@ -2910,6 +3127,8 @@ Layout layout(int32_t n) {
   // pruning: removed flags
   L.aux = off;
   off += align256((size_t)n * 4);
+  // lasso: 64-bit parent words over the mark and removed-flag arrays
+  L.parent = L.mark;
   // filtered stream sweeps: three change bitmaps and the accepting bitmap
   L.words = ((int64_t)n + 31) / 32;
   L.chg = off;
@@ -2923,6 +3142,10 @@ Layout layout(int32_t n) {
   off += align256(((size_t)n + 1) * 4);
   L.sums = off;
   off += align256((((size_t)n + 1 + kScanTile - 1) / kScanTile + 1) * 4);
+  L.counts = off;
+  off += 256;
+  L.ids = off;  // edge index of every CSR slot
+  off += align256((size_t)(m > 0 ? m : 0) * 4);
   size_t end_build = off;
   L.total = end_loop > end_build ? end_loop : end_build;
   return L;
@@ -3008,6 +3231,8 @@ int build_one(int32_t n, int64_t m, const int32_t* key, const int32_t* other, in
               int32_t* status, char* ws, const Layout& L, hipStream_t stream) {
   int32_t* cursor = reinterpret_cast<int32_t*>(ws + L.cursor);
   int32_t* sums = reinterpret_cast<int32_t*>(ws + L.sums);
+  int32_t* counts = reinterpret_cast<int32_t*>(ws + L.counts);
+  int32_t* ids = reinterpret_cast<int32_t*>(ws + L.ids);
   const int64_t len = (int64_t)n + 1;
   hipLaunchKernelGGL(fill_i32, dim3(grid_for(len, 256)), dim3(256), 0, stream, row_ptr, len, 0);
   if (m > 0)
@@ -3016,9 +3241,17 @@ int build_one(int32_t n, int64_t m, const int32_t* key, const int32_t* other, in
   hipLaunchKernelGGL(scan_tiles, dim3((unsigned)tiles), dim3(kScanThreads), 0, stream, row_ptr, len, sums);
   hipLaunchKernelGGL(scan_sums, dim3(1), dim3(1024), 0, stream, sums, tiles);
   hipLaunchKernelGGL(scan_add, dim3((unsigned)tiles), dim3(256), 0, stream, row_ptr, len, sums);
-  hipLaunchKernelGGL(copy_i32, dim3(grid_for(n, 256)), dim3(256), 0, stream, cursor, row_ptr, (int64_t)n);
-  if (m > 0)
-    hipLaunchKernelGGL(csr_scatter, dim3(grid_for(m, 256)), dim3(256), 0, stream, n, m, key, other, cursor, col);
+  if (m > 0) {
+    hipLaunchKernelGGL(copy_i32, dim3(grid_for(n, 256)), dim3(256), 0, stream, cursor, row_ptr, (int64_t)n);
+    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, stream, counts, (int64_t)2, 0);
+    hipLaunchKernelGGL(csr_scatter, dim3(grid_for(m, 256)), dim3(256), 0, stream, n, m, key, other, cursor, col, ids);
+    // the cursors are spent: their array holds the lists of longer rows
+    hipLaunchKernelGGL(csr_order_rows, dim3(grid_for(n, 256)), dim3(256), 0, stream, n, row_ptr, col, ids, cursor,
+                       counts);
+    hipLaunchKernelGGL(csr_order_mid, dim3(kOrderMidGrid), dim3(256), 0, stream, row_ptr, col, ids, cursor, counts);
+    hipLaunchKernelGGL(csr_order_long, dim3(kOrderLongGrid), dim3(kOrderThreads), 0, stream, n, row_ptr, col, ids,
+                       cursor, counts);
+  }
   return hipGetLastError() == hipSuccess ? MAP_OK : MAP_EDEVICE;
 }
 
@@ -3177,7 +3410,7 @@ extern "C" {
 size_t map_workspace_bytes(int32_t n, int64_t m, uint32_t flags) {
   (void)flags;
   if (!sizes_ok(n, m)) return 0;
-  return layout(n).total;
+  return layout(n, m).total;
 }
 
 int map_build_csr(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, int32_t* row_ptr, int32_t* col,
@@ -3186,7 +3419,7 @@ int map_build_csr(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, 
   if (!row_ptr || !status || !ws || (m > 0 && (!src || !dst || !col))) return MAP_EINVAL;
   if ((rrow_ptr == nullptr) != (rcol == nullptr)) return MAP_EINVAL;
   if (rrow_ptr && m > 0 && !rcol) return MAP_EINVAL;
-  const Layout L = layout(n);
+  const Layout L = layout(n, m);
   if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return MAP_ENOSPC;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s, status, (int64_t)1, (int32_t)MAP_OK);
@@ -3341,7 +3574,7 @@ int map_lasso(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t wit
   a.path = path;
   a.cap = path_cap;
   a.result = result;
-  a.parent = reinterpret_cast<int32_t*>(w + L.pv);
+  a.parent = reinterpret_cast<uint64_t*>(w + L.parent);
   a.front[0] = reinterpret_cast<int32_t*>(w + L.front0);
   a.front[1] = reinterpret_cast<int32_t*>(w + L.front1);
   a.ctrl = reinterpret_cast<Ctrl*>(w + L.ctrl);

@@ -113,3 +113,62 @@ def test_brute_force_lengths(seed):
                 continue
             assert (r.status, r.stem_len, r.cycle_len) == ("ok", stem, cyc)
             _check_path(g, r, w, init)
+
+
+def _all_walks(adj, a, b, k):
+    """Every walk of exactly k edges from a to b (k >= 1), as vertex lists."""
+    out = []
+
+    def go(path):
+        if len(path) == k + 1:
+            if path[-1] == b:
+                out.append(list(path))
+            return
+        for v in adj[path[-1]]:
+            path.append(v)
+            go(path)
+            path.pop()
+
+    go([a])
+    return out
+
+
+def _canonical(walks):
+    """Of several shortest walks, the one whose vertices read backwards are
+    lexicographically smallest."""
+    return min(walks, key=lambda p: p[::-1])
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_brute_force_canonical_paths(seed):
+    """Dense small digraphs with many shortest paths: every shortest walk is
+    enumerated and the backwards-smallest one must be the oracle's stem and
+    cycle (the choice depends on the edge set only, so a shuffled edge list
+    gives the same path)."""
+    rng = np.random.default_rng(2000 + seed)
+    n = int(rng.integers(3, 8))
+    m = int(rng.integers(n, 4 * n))
+    edges = [(int(rng.integers(1, n + 1)), int(rng.integers(1, n + 1))) for _ in range(m)]
+    g = synth.from_edges(n, edges, [])
+    shuffled = synth.from_edges(n, [edges[i] for i in rng.permutation(m)], [])
+    adj = {u: sorted({b for a, b in edges if a == u}) for u in range(1, n + 1)}
+    several = 0
+    for w in range(1, n + 1):
+        r = oracle.lasso(g, w, 0)
+        if r.status != "ok":
+            continue
+        walks = _all_walks(adj, w, w, r.cycle_len)
+        several += len(walks) > 1
+        assert r.path.tolist() == _canonical(walks)
+        for init in range(1, n + 1):
+            if init == w:
+                continue
+            r = oracle.lasso(g, w, init)
+            if r.status != "ok":
+                continue
+            stem = _canonical(_all_walks(adj, init, w, r.stem_len))
+            cyc = _canonical(_all_walks(adj, w, w, r.cycle_len))
+            assert r.path.tolist() == stem + cyc[1:], (init, w)
+            assert oracle.lasso(shuffled, w, init).path.tolist() == r.path.tolist()
+    if seed == 0:
+        assert several > 0

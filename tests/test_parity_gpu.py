@@ -311,36 +311,63 @@ def test_no_digest_flag(mc):
 
 # ---------------------------------------------------------------- CSR build
 
+def _stable_csr(n, key, other):
+    """Row pointer and columns of the CSR whose rows list their edges in
+    edge-list order: a stable sort of the edges by key (numpy's)."""
+    order = np.argsort(key, kind="stable")
+    deg = np.bincount(key - 1, minlength=n)
+    rp = np.concatenate([[0], np.cumsum(deg)])
+    return rp, (other[order] - 1).astype(np.int32)
+
+
 def test_csr_build_matches_edge_list(mc):
     g = synth.config2(seed=5, n=1 << 15, planted=True)
     csr = mc.build_csr(g.n, g.src, g.dst)
     assert int(csr.status.item()) == 0
     for rp, col, key, other in ((csr.row_ptr, csr.col, g.src, g.dst), (csr.rrow_ptr, csr.rcol, g.dst, g.src)):
-        rp = rp.cpu().numpy()
-        col = col.cpu().numpy()[:g.m]
-        deg = np.bincount(key - 1, minlength=g.n)
-        assert rp[0] == 0 and np.array_equal(np.diff(rp), deg)
-        # same multiset of (row, col) pairs
-        rows = np.repeat(np.arange(g.n), deg)
-        got = np.sort(rows.astype(np.int64) * g.n + col)
-        want = np.sort((key.astype(np.int64) - 1) * g.n + (other - 1))
-        assert np.array_equal(got, want)
+        want_rp, want_col = _stable_csr(g.n, key, other)
+        assert np.array_equal(rp.cpu().numpy(), want_rp)
+        assert np.array_equal(col.cpu().numpy()[:g.m], want_col)
 
 
 def _check_csr(csr, n, src, dst, orientations=2):
-    """Both CSRs hold exactly the in-range edges (ids 1..n at both ends)."""
+    """Both CSRs hold exactly the in-range edges (ids 1..n at both ends), each
+    row in edge-list order."""
     ok = (src >= 1) & (src <= n) & (dst >= 1) & (dst <= n)
     src, dst = src[ok], dst[ok]
     pairs = ((csr.row_ptr, csr.col, src, dst), (csr.rrow_ptr, csr.rcol, dst, src))[:orientations]
     for rp, col, key, other in pairs:
-        rp = rp.cpu().numpy()
-        deg = np.bincount(key - 1, minlength=n)
-        assert rp[0] == 0 and np.array_equal(np.diff(rp), deg)
-        col = col.cpu().numpy()[:len(key)]
-        rows = np.repeat(np.arange(n), deg)
-        got = np.sort(rows.astype(np.int64) * n + col)
-        want = np.sort((key.astype(np.int64) - 1) * n + (other - 1))
-        assert np.array_equal(got, want)
+        want_rp, want_col = _stable_csr(n, key, other)
+        assert np.array_equal(rp.cpu().numpy(), want_rp)
+        assert np.array_equal(col.cpu().numpy()[:len(key)], want_col)
+
+
+@pytest.mark.parametrize("order", ["random", "grouped"])
+def test_csr_build_row_order_every_length(mc, order):
+    """Rows of every length class the ordering passes distinguish (one lane
+    up to 16 edges, one wave up to 64, a workgroup in LDS up to 4096, chunked
+    merges beyond), each boundary from both sides, with the edge list shuffled
+    (slots reserved in schedule order) or grouped by key: every row in
+    edge-list order, and a second build byte-identical."""
+    import torch
+    rng = np.random.default_rng(31 if order == "random" else 32)
+    lengths = [0, 1, 2, 3, 15, 16, 17, 33, 63, 64, 65, 100, 1000, 4095, 4096, 4097, 8191, 8192, 8193, 20000,
+               100_003]
+    n = 5000
+    rows = rng.permutation(np.arange(1, n + 1))[:len(lengths)]
+    key = np.concatenate([np.full(d, r, np.int32) for d, r in zip(lengths, rows)]
+                         + [rng.integers(1, n + 1, 30_000).astype(np.int32)])
+    other = rng.integers(1, n + 1, len(key)).astype(np.int32)
+    perm = rng.permutation(len(key)) if order == "random" else np.argsort(key, kind="stable")
+    src, dst = key[perm].copy(), other[perm].copy()
+    print("csr row order", order, "n", n, "m", len(src), flush=True)
+    csr = mc.build_csr(n, src, dst)
+    assert int(csr.status.item()) == 0
+    _check_csr(csr, n, src, dst)
+    again = mc.build_csr(n, src, dst)
+    for a, b in ((csr.row_ptr, again.row_ptr), (csr.col, again.col), (csr.rrow_ptr, again.rrow_ptr),
+                 (csr.rcol, again.rcol)):
+        assert torch.equal(a, b)
 
 
 def _grouped(rng, n, max_deg, m_cap=None):
@@ -396,6 +423,23 @@ def test_csr_build_grid_stride(mc):
     csr = mc.build_csr(n, src, dst, transposed=False)
     assert int(csr.status.item()) == 0
     _check_csr(csr, n, src, dst, orientations=1)
+
+
+def test_csr_build_rows_past_one_grid_pass(mc):
+    """n = 2^25 vertices, more rows than one pass of the capped launch covers
+    (65,536 workgroups of 256 threads = 2^24): keys spread over the whole
+    range, many above 2^24, rows of every length class, shuffled."""
+    rng = np.random.default_rng(17)
+    n = 1 << 25
+    key = np.concatenate([rng.integers(1, n + 1, 150_000), rng.integers((1 << 24) + 1, n + 1, 150_000),
+                          np.full(40, n), np.full(5000, n - 1), np.full(70, 1 << 24), np.full(70, (1 << 24) + 1)])
+    other = rng.integers(1, n + 1, len(key))
+    perm = rng.permutation(len(key))
+    src, dst = key[perm].astype(np.int32), other[perm].astype(np.int32)
+    print("csr past one grid pass n", n, "m", len(src), flush=True)
+    csr = mc.build_csr(n, src, dst)
+    assert int(csr.status.item()) == 0
+    _check_csr(csr, n, src, dst)
 
 
 def test_csr_build_range_error(mc):
@@ -464,4 +508,8 @@ def test_config2_full_size(mc, key, planted):
 
 def test_config3_full_size(mc):
     g = synth.config3()
-    _check_golden(mc, g, _golden("c3"))
+    csr, _ = _check_golden(mc, g, _golden("c3"))
+    # the generator lists edges by source, so the pull CSR in edge order is
+    # the destination column as it stands
+    assert np.all(np.diff(g.src) >= 0)
+    assert np.array_equal(csr.col.cpu().numpy()[:g.m], g.dst - 1)
