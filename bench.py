@@ -611,7 +611,7 @@ def phase_table(ph, iterations):
     ph = ph.astype(np.float64)
     nb = ph.shape[0]
     ms = ph[:, :8].mean(axis=0) / 1e5          # ticks of 10 ns -> ms
-    total = float(ms.sum()) + float(ph[:, 12].mean() / 1e5)
+    total = float(ms.sum()) + float(ph[:, 12].mean() / 1e5) + float(ph[:, 13].mean() / 1e5)
     sweeps = ph[:, 8].mean()
     quiet = ph[:, 10].mean()
     lds = ph[:, 9].mean()
@@ -619,6 +619,8 @@ def phase_table(ph, iterations):
              for name, v in zip(PHASE_NAMES, ms)}
     rw = float(ph[:, 12].mean() / 1e5)
     table["remote_pass_wait"] = {"ms": round(rw, 3), "share": round(rw / total, 4) if total else None}
+    ga = float(ph[:, 13].mean() / 1e5)
+    table["remote_gather"] = {"ms": round(ga, 3), "share": round(ga / total, 4) if total else None}
     return {
         "workgroups": nb, "launch_ms": round(total, 3), "per_phase": table,
         "per_workgroup_sweeps": round(float(sweeps), 1), "quiet_sweep_share": round(float(quiet / sweeps), 4)
@@ -642,6 +644,8 @@ def main():
     ap.add_argument("--sync-sweeps", action="store_true", help="grid barrier after every sweep")
     ap.add_argument("--stream", action="store_true", help="stream the CSR every sweep (no on-chip staging)")
     ap.add_argument("--push", action="store_true", help="frontier rounds over the transposed CSR")
+    ap.add_argument("--direction", action="store_true",
+                    help="filtered sweeps switch to push rounds for small frontiers (builds the transposed CSR)")
     ap.add_argument("--batch-count", type=int, default=4096, help="graphs in the config-4 batch")
     ap.add_argument("--line-batch", type=int, default=512,
                     help="single-graph line: also run the first N config-4 graphs batched vs plain (0: skip)")
@@ -695,14 +699,17 @@ def main():
     ws = mc.workspace(n, m, device=dev)
     row_ptr = torch.empty(n + 1, dtype=torch.int32, device=dev)
     col = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
-    # The transposed CSR is built only where the path reads it (frontier rounds).
-    rrow_ptr = torch.empty(n + 1, dtype=torch.int32, device=dev) if args.push else None
-    rcol = torch.empty(max(m, 1), dtype=torch.int32, device=dev) if args.push else None
+    # The transposed CSR is built only where the path reads it (frontier rounds,
+    # the direction switch).
+    need_t = args.push or args.direction
+    rrow_ptr = torch.empty(n + 1, dtype=torch.int32, device=dev) if need_t else None
+    rcol = torch.empty(max(m, 1), dtype=torch.int32, device=dev) if need_t else None
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     res = mc.new_result(dev)
     stream = torch.cuda.current_stream()
     flags = mc.MAP_FLAG_NO_TRACE_DIGEST | (mc.MAP_FLAG_SYNC_SWEEPS if args.sync_sweeps else 0) | \
-        (mc.MAP_FLAG_STREAM if args.stream else 0) | (mc.MAP_FLAG_PUSH if args.push else 0)
+        (mc.MAP_FLAG_STREAM if args.stream else 0) | (mc.MAP_FLAG_PUSH if args.push else 0) | \
+        (mc.MAP_FLAG_DIRECTION if args.direction else 0)
 
     def step(ev=None):
         rc = mc.map_build_csr(n, src, dst, row_ptr, col, rrow_ptr, rcol, status, ws)

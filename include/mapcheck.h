@@ -94,6 +94,15 @@ extern "C" {
  * results are the same.  This flag turns that filter off (the previous
  * control applies: asynchronous unless MAP_FLAG_SYNC_SWEEPS). */
 #define MAP_FLAG_NO_FILTER 0x40u
+/* map_propagate, map_detect: direction switch of the filtered sweeps above
+ * (push or pull by frontier size, after direction-optimizing breadth-first
+ * search).  A sweep whose previous sweep grew fewer than n/16 rows runs as a
+ * push round instead: each row that grew raises its predecessors, read from
+ * the transposed CSR, with an atomic max; larger frontiers keep the pull over
+ * every row.  The results are the same.  Needs rrow_ptr and rcol (else
+ * MAP_EINVAL); MAP_EINVAL with MAP_FLAG_PUSH; ignored with MAP_FLAG_DENSE_ONLY
+ * and wherever the filtered sweeps do not run. */
+#define MAP_FLAG_DIRECTION 0x80u
 
 /* Result of map_propagate / map_detect, written to device memory (32 bytes). */
 typedef struct map_result {
@@ -409,7 +418,9 @@ int map_engine_destroy(map_engine *e);
  * detect and strip (with its barrier), and the rest; then the counts of sweeps,
  * LDS passes, quiet sweeps and iterations; then the ticks spent waiting, after
  * a resident remote pass, for the workgroup's other waves to finish theirs;
- * 3 words unused.  Copies
+ * the ticks of the gather part of asynchronous resident remote passes (the
+ * rest of those passes, clearing and row updates, stays in the second word);
+ * 2 words unused.  Copies
  * min(*blocks, max_blocks) workgroups to host memory `out` (synchronous, after
  * the launch has finished) and sets *blocks to the launch's workgroup count.
  * MAP_EINVAL in the normal build. */

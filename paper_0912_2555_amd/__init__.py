@@ -53,6 +53,7 @@ MAP_FLAG_SYNC_SWEEPS = 0x8
 MAP_FLAG_PUSH = 0x10
 MAP_FLAG_EARLY = 0x20
 MAP_FLAG_NO_FILTER = 0x40
+MAP_FLAG_DIRECTION = 0x80
 MAP_NOALLOC_MAX_N = 1 << 22
 
 EXPORTS = ("map_workspace_bytes", "map_build_csr", "map_propagate", "map_detect", "map_batch_workspace_bytes",

@@ -52,8 +52,13 @@ constexpr int kSortPerLane = kSortSlots / kWave;
 static_assert(kSortSlots >= kWave * kGatherBatch, "sort must cover a gather batch");
 constexpr uint32_t kAllFlags =
     MAP_FLAG_DENSE_ONLY | MAP_FLAG_NO_TRACE_DIGEST | MAP_FLAG_STREAM | MAP_FLAG_SYNC_SWEEPS | MAP_FLAG_PUSH |
-    MAP_FLAG_EARLY | MAP_FLAG_NO_FILTER;
+    MAP_FLAG_EARLY | MAP_FLAG_NO_FILTER |
+    MAP_FLAG_DIRECTION;
 constexpr uint32_t kAccBit = 0x80000000u;
+#ifndef MAPCHECK_PUSH_DIV
+#define MAPCHECK_PUSH_DIV 16
+#endif
+constexpr int kPushDiv = MAPCHECK_PUSH_DIV;  // direction switch: push rounds while the previous sweep grew fewer than n / kPushDiv rows
 constexpr int kHubEdges = 64;  // stream tiles: default edges of a row in a staged chunk above which a wave folds it
 
 // Global-memory views of device pointers, for out-of-line functions where the
@@ -321,6 +326,7 @@ struct LoopArgs {
   uint32_t* accb;        // [words]
   int64_t words;         // 32-bit words per bitmap
   int32_t filt;          // 1: run the filtered stream kernel
+  int32_t dopt;          // filtered stream kernel: small frontiers run as push rounds (transposed CSR, front[])
   int32_t hub;           // stream tiles: rows with more edges in a staged chunk are folded by the whole wave
 };
 
@@ -386,7 +392,7 @@ __shared__ int32_t g_rpre[kWavesPerBlock + 1];
 // events; the block writes its totals to g_phase_out when it finishes.
 enum PhaseSlot {
   kPhSetup, kPhRemote, kPhLocal, kPhStream, kPhReport, kPhWait, kPhDetect, kPhOther,
-  kPhSweeps, kPhLocalPasses, kPhQuiet, kPhIters, kPhRemoteWait, kPhSlots = 16
+  kPhSweeps, kPhLocalPasses, kPhQuiet, kPhIters, kPhRemoteWait, kPhGather, kPhSlots = 16
 };
 __shared__ uint64_t g_ph[kPhSlots];
 __shared__ uint64_t g_ph_t;
@@ -626,10 +632,14 @@ __device__ __forceinline__ void gather_block(const uint8_t* acc, uint32_t* best_
   const int32_t total = g_rpre[kWavesPerBlock];
   const int32_t share = (total + kWavesPerBlock - 1) / kWavesPerBlock;
   const int32_t lo = min(total, wib * share), hi = min(total, lo + share);
+  // The list that holds the wave's first edge (the last one whose prefix sum
+  // does not exceed it), found once: a lane's later edges only move forward.
+  int w_lo = 0;
+  while (w_lo + 1 < kWavesPerBlock && lo >= g_rpre[w_lo + 1]) ++w_lo;
   for (int32_t g0 = lo; g0 < hi; g0 += kWave * kGatherBatch) {
     uint32_t e[kGatherBatch];
     int32_t seg[kGatherBatch];
-    int w = 0;  // the list a lane's next edge lies in (its edges increase)
+    int w = w_lo;  // the list a lane's next edge lies in (its edges increase)
 #pragma unroll
     for (int u = 0; u < kGatherBatch; ++u) {
       const int32_t gi = g0 + lane + u * kWave;
@@ -776,6 +786,7 @@ __device__ uint32_t sweep_resident(const LoopArgs& a, const uint8_t* acc, const 
   if (kBal) {
     __syncthreads();  // every wave's maxima cleared before any wave folds into them
     gather_block<kFirst ? 0 : 1>(acc, &R.best[0][0], a, wib, lane, cur);
+    if (!kFirst) PH_MARK(kPhGather);
   } else {
     wave_lds_sync();
     gather_range<kFirst ? 0 : 1>(acc, W.we0, W.wr, best, a, lane, cur);
@@ -887,6 +898,20 @@ __device__ uint32_t sweep_rows(const LoopArgs& a, const uint8_t* acc, const Wave
   return ch;
 }
 
+// Appends v (where take) to frontier F with one counter update per wave;
+// returns the number appended by the wave (wave-uniform).
+__device__ __forceinline__ uint32_t frontier_append(int32_t* F, uint32_t* cnt, bool take, int32_t v, int lane) {
+  const uint64_t m = __ballot(take);
+  if (m == 0) return 0;
+  const int first = __ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0;
+  if (lane == first) base = __hip_atomic_fetch_add(cnt, (uint32_t)__popcll(m), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  base = (uint32_t)__shfl((int)base, first, kWave);
+  const uint64_t below = lane ? (~0ull >> (kWave - lane)) : 0ull;
+  if (take) F[base + (uint32_t)__popcll(m & below)] = v;
+  return (uint32_t)__popcll(m);
+}
+
 // Sets, with one atomic per 32-bit word, the bits of bitmap `mark` for the
 // rows v0 + l (l = 0..63) whose lane l is set in m (wave-uniform m).
 __device__ __forceinline__ void mark_rows(uint32_t* mark, int64_t v0, unsigned long long m, int lane) {
@@ -910,7 +935,8 @@ __device__ __forceinline__ bool bit_set(const uint32_t* b, uint32_t v) { return 
 // successor left out either sends nothing new (not accepting) or has not grown
 // since the previous sweep, whose rows already folded in its value: the
 // fixpoint is unchanged.  The rows that grow (in the reset sweep: that get a
-// nonzero value) are set in `mark` for the next sweep.
+// nonzero value) are set in `mark` for the next sweep.  Returns the rows that
+// grew (the wave's count).
 template <bool kFirst>
 __device__ uint32_t sweep_tile_filt(const LoopArgs& a, const uint8_t* acc, int64_t r0, int64_t r1, TileLds& L,
                                     int lane, uint32_t cur, uint32_t* acc_count, const uint32_t* keep,
@@ -953,7 +979,7 @@ __device__ uint32_t sweep_tile_filt(const LoopArgs& a, const uint8_t* acc, int64
     fold_chunk<kRowsPerLane>(L.val, lo, hi, c0, cnt, a.hub, lane, best);
     wave_lds_sync();
   }
-  uint32_t changed = 0, nacc = 0;
+  uint32_t grown = 0, nacc = 0;
 #pragma unroll
   for (int j = 0; j < kRowsPerLane; ++j) {
     int r = lane + j * kWave;
@@ -964,18 +990,61 @@ __device__ uint32_t sweep_tile_filt(const LoopArgs& a, const uint8_t* acc, int64
         uint32_t isacc = gacc[v] ? 1u : 0u;
         nacc += isacc;
         pv[v] = (isacc << 31) | cur | best[j];
-        changed |= (best[j] | isacc) != 0;
         grew = best[j] != 0;
       } else if (best[j] > (old[j] & vmask)) {
         pv[v] = (old[j] & ~vmask) | best[j];
-        changed = 1;
         grew = true;
       }
     }
-    mark_rows(mark, r0 + j * kWave, __ballot(grew), lane);
+    const unsigned long long gm = __ballot(grew);
+    mark_rows(mark, r0 + j * kWave, gm, lane);
+    grown += (uint32_t)__popcll(gm);
   }
   if (acc_count) *acc_count += nacc;
-  return __ballot(changed) != 0;
+  return grown;
+}
+
+// Filtered stream mode, direction switch (dopt): a sweep whose frontier (the
+// rows that grew in the previous sweep, set in `keep`) is small runs as a
+// push round over the transposed CSR instead of a pull over every row.  Each
+// lane scans one word of `keep` per step and, for every row w set in it,
+// raises each predecessor v with an atomic max of what w sends, behind v's
+// own accepting bit and the iteration tag (the reset sweep wrote every row
+// with both, so the words compare by value); a predecessor that grows is set
+// in `mark`.  The result is that of the filtered pull: both fold, into each
+// row, what its grown successors send.  Returns the wave's count of raises
+// that grew a row (a row raised twice counts twice: an upper bound on the
+// next frontier, zero exactly when nothing grew).
+__device__ __forceinline__ uint32_t push_round_filt(const LoopArgs& a, const uint32_t* keep, uint32_t* mark,
+                                                 uint32_t cur, int64_t gw, int64_t nw, int lane) {
+  g_u32* pvg = (g_u32*)a.pv;
+  g_ci32* rrow = (g_ci32*)a.rrow_ptr;
+  g_ci32* rcol = (g_ci32*)a.rcol;
+  const uint32_t n = (uint32_t)a.n;
+  uint32_t grew = 0;
+  for (int64_t w0 = gw * kWave; w0 < a.words; w0 += nw * kWave) {
+    const int64_t wi = w0 + lane;
+    uint32_t bits = wi < a.words ? keep[wi] : 0u;
+    while (bits) {
+      const uint32_t w = (uint32_t)(wi << 5) + (uint32_t)__builtin_ctz(bits);
+      bits &= bits - 1u;
+      if (w >= n) break;
+      const uint32_t x = sent_word(pvg[w], (int32_t)w, cur, a.val_mask, a.tag_mask);
+      if (!x) continue;
+      const int32_t k1 = rrow[w + 1];
+      for (int32_t k = rrow[w]; k < k1; ++k) {
+        const int32_t v = rcol[k];
+        if ((uint32_t)v >= n) continue;
+        const uint32_t word = (bit_set(a.accb, (uint32_t)v) ? kAccBit : 0u) | cur | x;
+        const uint32_t old = __hip_atomic_fetch_max(&a.pv[v], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((old & a.val_mask) < x) {
+          atomicOr(&mark[v >> 5], 1u << (v & 31));
+          ++grew;
+        }
+      }
+    }
+  }
+  return wave_sum_u32(grew);
 }
 
 // One filtered stream sweep of the wave's rows, in tiles in the order values
@@ -988,11 +1057,11 @@ __device__ uint32_t sweep_stream_filt(const LoopArgs& a, const uint8_t* acc, con
     const int64_t last = W.r0 + ((W.r1 - W.r0 - 1) / kTileRows) * kTileRows;
     if (W.ascending) {
       for (int64_t t0 = W.r0; t0 <= last; t0 += kTileRows)
-        ch |= sweep_tile_filt<kFirst>(a, acc, t0, min(W.r1, t0 + kTileRows), g_lds.tile[wib], lane, cur, acc_count,
+        ch += sweep_tile_filt<kFirst>(a, acc, t0, min(W.r1, t0 + kTileRows), g_lds.tile[wib], lane, cur, acc_count,
                                       keep, mark);
     } else {
       for (int64_t t0 = last; t0 >= W.r0; t0 -= kTileRows)
-        ch |= sweep_tile_filt<kFirst>(a, acc, t0, min(W.r1, t0 + kTileRows), g_lds.tile[wib], lane, cur, acc_count,
+        ch += sweep_tile_filt<kFirst>(a, acc, t0, min(W.r1, t0 + kTileRows), g_lds.tile[wib], lane, cur, acc_count,
                                       keep, mark);
     }
   }
@@ -1069,20 +1138,6 @@ __device__ void sort_gather_batches(int32_t we0, int32_t we1, int lane) {
       if (i < cnt) R.e[k0 + i] = key[u];
     }
   }
-}
-
-// Appends v (where take) to frontier F with one counter update per wave;
-// returns the number appended by the wave (wave-uniform).
-__device__ __forceinline__ uint32_t frontier_append(int32_t* F, uint32_t* cnt, bool take, int32_t v, int lane) {
-  const uint64_t m = __ballot(take);
-  if (m == 0) return 0;
-  const int first = __ffsll((unsigned long long)m) - 1;
-  uint32_t base = 0;
-  if (lane == first) base = __hip_atomic_fetch_add(cnt, (uint32_t)__popcll(m), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  base = (uint32_t)__shfl((int)base, first, kWave);
-  const uint64_t below = lane ? (~0ull >> (kWave - lane)) : 0ull;
-  if (take) F[base + (uint32_t)__popcll(m & below)] = v;
-  return (uint32_t)__popcll(m);
 }
 
 // The whole MAP computation for one graph, run by `nb` cooperating blocks of
@@ -1254,6 +1309,17 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     for (int i = 0; i < kWavesPerBlock; ++i) any |= s_red[i];
     __syncthreads();
     return any ? 1u : 0u;
+  };
+  // Filtered stream sweeps report how many rows grew (the barrier sums them):
+  // the next sweep's frontier size.
+  auto block_count = [&](uint32_t x) {
+    if (lane == 0) s_red[wib] = x;
+    wave_writes_done();
+    __syncthreads();
+    uint32_t t = 0;
+    for (int i = 0; i < kWavesPerBlock; ++i) t += s_red[i];
+    __syncthreads();
+    return t;
   };
 
   uint32_t count_prev = 0;  // |A_k| of the last completed iteration
@@ -1478,7 +1544,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
       }
       s = 1;
       early_scan();
-      const uint32_t any1 = block_any(c1);
+      const uint32_t any1 = kFilt ? block_count(c1) : block_any(c1);
       if (!report(any1, d0)) goto aborted;
       PH_MARK(kPhReport);
       PH_COUNT(kPhSweeps, 1);
@@ -1534,15 +1600,24 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
       uint32_t c2;
       if (kFilt) {
         clear_share(a.chg + ((gsw + 1) % 3) * a.words, a.words, b, nb);
-        c2 = sweep_stream_filt<false>(a, acc, W, wib, lane, cur, nullptr, a.chg + ((gsw + 2) % 3) * a.words,
-                                      a.chg + (gsw % 3) * a.words);
+        uint32_t* markb = a.chg + (gsw % 3) * a.words;
+        const uint32_t* keepb = a.chg + ((gsw + 2) % 3) * a.words;
+        // tot: the rows that grew in the previous sweep (an upper bound after a
+        // push round), the same in every block
+        if (a.dopt && (int64_t)tot * kPushDiv < (int64_t)a.n) {
+          const int64_t gw = (int64_t)b * kWavesPerBlock + wib, nw = (int64_t)nb * kWavesPerBlock;
+          c2 = push_round_filt(a, keepb, markb, cur, gw, nw, lane);
+          PH_MARK(kPhStream);
+        } else {
+          c2 = sweep_stream_filt<false>(a, acc, W, wib, lane, cur, nullptr, keepb, markb);
+        }
         ++gsw;
       } else {
         c2 = sweep_rows<false, kBal>(a, acc, W, wib, lane, cur, nullptr, &local_fix);
       }
       s++;
       early_scan();
-      const uint32_t any2 = block_any(c2);
+      const uint32_t any2 = kFilt ? block_count(c2) : block_any(c2);
       if (!report(any2, d0)) goto aborted;
       PH_MARK(kPhReport);
       PH_COUNT(kPhSweeps, 1);
@@ -1574,15 +1649,37 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
       unsigned long long dig = 0;
       uint32_t nz = 0;
       const bool want_digest = a.digest != 0;
-      for_own_rows(a, W, lane, [&](int64_t v, uint32_t x) {
-        uint32_t mv = x & a.val_mask;
-        uint32_t id = (uint32_t)v + 1u;
+      auto note = [&](int64_t v, uint32_t mv) {
+        const uint32_t id = (uint32_t)v + 1u;
         if (mv == id) wit = max(wit, (int32_t)id);
         if (want_digest) dig += mix64(((unsigned long long)id << 32) | mv);
         nz |= mv;
-        // Many vertices share a map value: read before writing.
-        if (mv != 0 && acc[mv - 1]) acc[mv - 1] = 0;
-      });
+      };
+      if (W.resident) {
+        // Every flag of the lane's rows is read before any is cleared, so the
+        // reads overlap (rows that share a map value clear it twice, which is
+        // harmless).
+        uint32_t mvs[kResRowsPerLane];
+        uint8_t fl[kResRowsPerLane];
+#pragma unroll
+        for (int j = 0; j < kResRowsPerLane; ++j) {
+          const int64_t v = W.r0 + lane + j * kWave;
+          mvs[j] = v < W.r1 ? g_lds.res.pv[v - W.rb0] & a.val_mask : 0u;
+          if (v < W.r1) note(v, mvs[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < kResRowsPerLane; ++j) fl[j] = mvs[j] ? acc[mvs[j] - 1] : (uint8_t)0;
+#pragma unroll
+        for (int j = 0; j < kResRowsPerLane; ++j)
+          if (fl[j]) acc[mvs[j] - 1] = 0;
+      } else {
+        for_own_rows(a, W, lane, [&](int64_t v, uint32_t x) {
+          const uint32_t mv = x & a.val_mask;
+          note(v, mv);
+          // Many vertices share a map value: read before writing.
+          if (mv != 0 && acc[mv - 1]) acc[mv - 1] = 0;
+        });
+      }
       wit = wave_max_i32(wit);
       if (want_digest) dig = wave_sum_u64(dig);
       const uint32_t wnz = __ballot(nz != 0) != 0 ? 1u : 0u;
@@ -3208,6 +3305,7 @@ int launch_loop(LoopArgs& a, hipStream_t stream) {
   const int64_t rpw = (rpb + kWavesPerBlock - 1) / kWavesPerBlock;
   const bool all_stream = a.force_stream || a.n >= (1 << 24) || rpw > kResWaveRows;
   a.filt = (a.chg != nullptr && !a.early && !a.push && all_stream) ? 1 : 0;
+  if (!a.filt) a.dopt = 0;
   const bool async = !a.filt && grid > 1 && !a.sync_sweeps && a.tag_mask != 0 && !a.early;
   const void* kernel =
       a.early ? reinterpret_cast<const void*>(map_loop_kernel<false, true>)
@@ -3479,6 +3577,20 @@ static int push_setup(LoopArgs& a, const int32_t* rrow_ptr, const int32_t* rcol,
   return MAP_OK;
 }
 
+// Direction switch of the filtered stream sweeps (MAP_FLAG_DIRECTION, not with
+// MAP_FLAG_DENSE_ONLY): needs the transposed CSR; the frontier is the change
+// bitmap the sweeps keep anyway.  It takes effect only where the filtered
+// stream kernel runs (launch_loop).
+static int dir_setup(LoopArgs& a, const int32_t* rrow_ptr, const int32_t* rcol, uint32_t flags) {
+  if (!(flags & MAP_FLAG_DIRECTION) || (flags & MAP_FLAG_DENSE_ONLY)) return MAP_OK;
+  if (flags & MAP_FLAG_PUSH) return MAP_EINVAL;
+  if (!rrow_ptr || !rcol) return MAP_EINVAL;
+  a.dopt = 1;
+  a.rrow_ptr = rrow_ptr;
+  a.rcol = rcol;
+  return MAP_OK;
+}
+
 int map_propagate(int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* rrow_ptr, const int32_t* rcol,
                   const uint8_t* accepting, int32_t* map_out, map_result* result, uint32_t flags, void* ws,
                   size_t ws_bytes, void* stream) {
@@ -3493,6 +3605,8 @@ int map_propagate(int32_t n, const int32_t* row_ptr, const int32_t* col, const i
   if (flags & MAP_FLAG_NO_FILTER) a.chg = nullptr;
   a.map_out = map_out;
   rc = push_setup(a, rrow_ptr, rcol, flags, ws);
+  if (rc) return rc;
+  rc = dir_setup(a, rrow_ptr, rcol, flags);
   if (rc) return rc;
   return launch_loop(a, reinterpret_cast<hipStream_t>(stream));
 }
@@ -3517,6 +3631,8 @@ int map_detect(int32_t n, const int32_t* row_ptr, const int32_t* col, const int3
   if (flags & MAP_FLAG_NO_FILTER) a.chg = nullptr;
   rc = push_setup(a, rrow_ptr, rcol, flags, ws);
   if (rc) return rc;
+  rc = dir_setup(a, rrow_ptr, rcol, flags);
+  if (rc) return rc;
   if (flags & MAP_FLAG_EARLY) {
     if (a.push) return MAP_EINVAL;
     a.early = 1;
@@ -3528,7 +3644,7 @@ int map_detect_noalloc(int32_t n, const int32_t* row_ptr, const int32_t* col, co
                        map_result* result, uint64_t* trace, int32_t trace_cap, uint8_t* accepting_out,
                        int32_t max_iterations, uint32_t flags, void* stream) {
   if (flags & ~kAllFlags) return MAP_EINVAL;
-  if ((flags & MAP_FLAG_PUSH) && !(flags & MAP_FLAG_DENSE_ONLY)) return MAP_EINVAL;
+  if ((flags & (MAP_FLAG_PUSH | MAP_FLAG_DIRECTION)) && !(flags & MAP_FLAG_DENSE_ONLY)) return MAP_EINVAL;
   if (trace && trace_cap < 0) return MAP_EINVAL;
   if (n < 1 || n > MAP_NOALLOC_MAX_N) return MAP_ERANGE;
   if (!row_ptr || !col || !accepting0 || !result) return MAP_EINVAL;

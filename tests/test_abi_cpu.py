@@ -88,7 +88,10 @@ def test_host_side_errors_without_device(lib):
                              None) == MAP_ENOSPC
     assert lib.map_propagate(5, None, fake, None, None, fake, fake, fake, 0, fake, big, None) == MAP_EINVAL
     assert lib.map_propagate(5, fake, fake, None, None, fake, None, fake, 0, fake, big, None) == MAP_EINVAL
+    assert lib.map_propagate(5, fake, fake, None, None, fake, fake, fake, 0x100, fake, big, None) == MAP_EINVAL
+    # MAP_FLAG_DIRECTION needs the transposed CSR and excludes MAP_FLAG_PUSH
     assert lib.map_propagate(5, fake, fake, None, None, fake, fake, fake, 0x80, fake, big, None) == MAP_EINVAL
+    assert lib.map_propagate(5, fake, fake, fake, fake, fake, fake, fake, 0x90, fake, big, None) == MAP_EINVAL
     assert lib.map_detect(0, fake, fake, None, None, fake, fake, None, 0, None, 0, 0, fake, big, None) == MAP_ERANGE
     assert lib.map_detect(5, fake, fake, None, None, None, fake, None, 0, None, 0, 0, fake, big, None) == MAP_EINVAL
     assert lib.map_detect(5, fake, fake, None, None, fake, None, None, 0, None, 0, 0, fake, big, None) == MAP_EINVAL
@@ -96,7 +99,9 @@ def test_host_side_errors_without_device(lib):
     assert lib.map_detect(5, fake, fake, None, None, fake, fake, None, 0, None, 0, 0, fake, 8, None) == MAP_ENOSPC
     # MAP_FLAG_EARLY with MAP_FLAG_PUSH (frontier rounds) is refused before anything is enqueued
     assert lib.map_detect(5, fake, fake, fake, fake, fake, fake, None, 0, None, 0, 0x30, fake, big, None) == MAP_EINVAL
-    assert lib.map_detect(5, fake, fake, fake, fake, fake, fake, None, 0, None, 0, 0x80, fake, big, None) == MAP_EINVAL
+    assert lib.map_detect(5, fake, fake, fake, fake, fake, fake, None, 0, None, 0, 0x100, fake, big, None) == MAP_EINVAL
+    assert lib.map_detect(5, fake, fake, None, None, fake, fake, None, 0, None, 0, 0x80, fake, big, None) == MAP_EINVAL
+    assert lib.map_detect(5, fake, fake, fake, fake, fake, fake, None, 0, None, 0, 0x90, fake, big, None) == MAP_EINVAL
 
 
 def test_noalloc_host_side_errors_without_device(lib):
@@ -109,6 +114,7 @@ def test_noalloc_host_side_errors_without_device(lib):
     assert lib.map_detect_noalloc(5, None, fake, fake, fake, None, 0, None, 0, 0, None) == MAP_EINVAL
     assert lib.map_detect_noalloc(5, fake, fake, None, fake, None, 0, None, 0, 0, None) == MAP_EINVAL
     assert lib.map_detect_noalloc(5, fake, fake, fake, None, None, 0, None, 0, 0, None) == MAP_EINVAL
+    assert lib.map_detect_noalloc(5, fake, fake, fake, fake, None, 0, None, 0, 0x100, None) == MAP_EINVAL
     assert lib.map_detect_noalloc(5, fake, fake, fake, fake, None, 0, None, 0, 0x80, None) == MAP_EINVAL
     assert lib.map_detect_noalloc(5, fake, fake, fake, fake, None, 0, None, 0, 0x10, None) == MAP_EINVAL
     assert lib.map_detect_noalloc(5, fake, fake, fake, fake, fake, -1, None, 0, 0, None) == MAP_EINVAL

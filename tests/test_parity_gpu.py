@@ -141,6 +141,53 @@ def test_filtered_stream_full_vectors(mc, g):
     check_propagate_all(mc, g, max_k=8, flags=mc.MAP_FLAG_STREAM)
 
 
+def _chain_graph(n, acc_every):
+    """v -> v+1 for every v, accepting every acc_every-th vertex: each sweep
+    grows a handful of rows (push rounds throughout the direction switch)."""
+    edges = [(v, v + 1) for v in range(1, n)] + [(n, 1)] * (n % 7 == 0)
+    return synth.from_edges(n, edges, range(acc_every, n + 1, acc_every), f"chain{n}")
+
+
+@pytest.mark.parametrize("g", [synth.config3(n=1 << 16), synth.config2(seed=8, n=1 << 13, planted=True),
+                               synth.config2(seed=9, n=1 << 15), synth.config1(), synth.config1(dag=True),
+                               _chain_graph(3000, 250), _chain_graph(2800, 97)], ids=lambda g: g.name)
+def test_direction_switch_full_vectors(mc, g):
+    """Filtered stream sweeps with the direction switch (push rounds from the
+    rows that grew while they are fewer than n/16, pull sweeps otherwise):
+    every iteration's full map vector and the whole detection equal the
+    oracle's."""
+    flags = mc.MAP_FLAG_STREAM | mc.MAP_FLAG_DIRECTION
+    csr = mc.build_csr(g.n, g.src, g.dst)
+    check_propagate_all(mc, g, csr, max_k=6, flags=flags)
+    check_detect(mc, g, csr, flags=flags)
+
+
+def test_direction_switch_dense_and_hubs(mc):
+    """Dense random digraphs (frontiers large enough for pull sweeps between
+    push rounds) and the hub graph (a push from a row with 50,000
+    predecessors)."""
+    rng = np.random.default_rng(41)
+    for n, deg in ((5000, 8), (40000, 3)):
+        src = rng.integers(1, n + 1, n * deg).astype(np.int32)
+        dst = rng.integers(1, n + 1, n * deg).astype(np.int32)
+        acc = (rng.random(n) < 0.05).astype(np.uint8)
+        g = synth.Graph(n=n, src=src, dst=dst, acc=acc, name=f"dense{n}x{deg}")
+        csr = mc.build_csr(g.n, g.src, g.dst)
+        check_detect(mc, g, csr, flags=mc.MAP_FLAG_STREAM | mc.MAP_FLAG_DIRECTION)
+        check_propagate_all(mc, g, csr, max_k=3, flags=mc.MAP_FLAG_STREAM | mc.MAP_FLAG_DIRECTION)
+    g = hub_graph()
+    csr = mc.build_csr(g.n, g.src, g.dst)
+    check_detect(mc, g, csr, flags=mc.MAP_FLAG_STREAM | mc.MAP_FLAG_DIRECTION)
+    check_propagate_all(mc, g, csr, max_k=2, flags=mc.MAP_FLAG_STREAM | mc.MAP_FLAG_DIRECTION)
+
+
+def test_direction_switch_needs_transposed(mc):
+    g = synth.config1()
+    csr = mc.build_csr(g.n, g.src, g.dst, transposed=False)
+    with pytest.raises(mc.MapError):
+        mc.detect(csr, g.acc, flags=mc.MAP_FLAG_DIRECTION)
+
+
 @pytest.mark.parametrize("n,planted", [(1 << 14, False), (1 << 14, True), (1 << 16, False), (1 << 16, True)])
 def test_config2_reduced(mc, n, planted):
     g = synth.config2(seed=2, n=n, planted=planted)
@@ -157,6 +204,7 @@ def test_config3_reduced(mc):
     _, ref = check_detect(mc, g, csr)
     check_propagate_all(mc, g, csr, max_k=2)
     check_detect(mc, g, csr, flags=mc.MAP_FLAG_PUSH, ref=ref)
+    check_detect(mc, g, csr, flags=mc.MAP_FLAG_STREAM | mc.MAP_FLAG_DIRECTION, ref=ref)
 
 
 @pytest.mark.parametrize("g", [c for c in _random_cases() if c.n >= 64] + [synth.config1(), synth.config1(dag=True),
