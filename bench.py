@@ -645,7 +645,9 @@ def main():
     ap.add_argument("--stream", action="store_true", help="stream the CSR every sweep (no on-chip staging)")
     ap.add_argument("--push", action="store_true", help="frontier rounds over the transposed CSR")
     ap.add_argument("--direction", action="store_true",
-                    help="filtered sweeps switch to push rounds for small frontiers (builds the transposed CSR)")
+                    help="filtered sweeps switch to push rounds for small frontiers (builds the transposed CSR); "
+                         "on by default for config 3")
+    ap.add_argument("--pull-only", action="store_true", help="config 3 without the direction switch")
     ap.add_argument("--batch-count", type=int, default=4096, help="graphs in the config-4 batch")
     ap.add_argument("--line-batch", type=int, default=512,
                     help="single-graph line: also run the first N config-4 graphs batched vs plain (0: skip)")
@@ -701,7 +703,9 @@ def main():
     col = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
     # The transposed CSR is built only where the path reads it (frontier rounds,
     # the direction switch).
-    need_t = args.push or args.direction
+    # Config 3 runs its filtered sweeps with the direction switch unless told not to.
+    direction = not args.push and (args.direction or (args.workload == "c3" and not args.pull_only))
+    need_t = args.push or direction
     rrow_ptr = torch.empty(n + 1, dtype=torch.int32, device=dev) if need_t else None
     rcol = torch.empty(max(m, 1), dtype=torch.int32, device=dev) if need_t else None
     status = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -709,7 +713,7 @@ def main():
     stream = torch.cuda.current_stream()
     flags = mc.MAP_FLAG_NO_TRACE_DIGEST | (mc.MAP_FLAG_SYNC_SWEEPS if args.sync_sweeps else 0) | \
         (mc.MAP_FLAG_STREAM if args.stream else 0) | (mc.MAP_FLAG_PUSH if args.push else 0) | \
-        (mc.MAP_FLAG_DIRECTION if args.direction else 0)
+        (mc.MAP_FLAG_DIRECTION if direction else 0)
 
     def step(ev=None):
         rc = mc.map_build_csr(n, src, dst, row_ptr, col, rrow_ptr, rcol, status, ws)

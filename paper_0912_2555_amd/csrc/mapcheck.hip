@@ -2828,6 +2828,10 @@ __global__ void __launch_bounds__(1024) batch_plan(int32_t count, const map_grap
 
 // --------------------------------------------------------------- CSR build --
 
+// CSR build: the path a build takes, chosen on the device (csr_pick) and read
+// by every kernel of both paths, which return at once when it is not theirs.
+constexpr int32_t kBuildAtomic = 1;  // per-row cursors, one atomic per run of equal keys, then row ordering
+constexpr int32_t kBuildRadix = 2;   // stable radix sort by key (keys mostly differ from their neighbour's)
 constexpr int kScanThreads = 256;
 constexpr int kScanPer = 16;
 constexpr int kScanTile = kScanThreads * kScanPer;
@@ -2874,8 +2878,9 @@ __device__ __forceinline__ KeyRun key_run(bool valid, int32_t k, int lane) {
 
 // Degree histogram of the key endpoint: cnt[key] += (edges with that key)
 // (cnt = row_ptr, so row v's count lands at index v+1 for 1-based key v+1).
-__global__ void csr_hist(int32_t n, int64_t m, const int32_t* __restrict__ key, const int32_t* __restrict__ other,
-                         int32_t* cnt, int32_t* status) {
+__global__ void csr_hist(const int32_t* gate, int32_t n, int64_t m, const int32_t* __restrict__ key,
+                         const int32_t* __restrict__ other, int32_t* cnt, int32_t* status) {
+  if (*gate != kBuildAtomic) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t w0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); w0 < m; w0 += stride) {
@@ -2894,7 +2899,9 @@ __global__ void csr_hist(int32_t n, int64_t m, const int32_t* __restrict__ key, 
 }
 
 // In-place inclusive scan of each tile of kScanTile elements; tile totals to sums.
-__global__ void __launch_bounds__(kScanThreads) scan_tiles(int32_t* a, int64_t len, int32_t* sums) {
+__global__ void __launch_bounds__(kScanThreads) scan_tiles(const int32_t* gate, int32_t want, int32_t* a, int64_t len,
+                                                          int32_t* sums) {
+  if (*gate != want) return;
   __shared__ int32_t part[kScanThreads];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
   int32_t x[kScanPer];
@@ -2923,7 +2930,8 @@ __global__ void __launch_bounds__(kScanThreads) scan_tiles(int32_t* a, int64_t l
 }
 
 // Exclusive scan of the tile totals by one workgroup.
-__global__ void __launch_bounds__(1024) scan_sums(int32_t* sums, int64_t count) {
+__global__ void __launch_bounds__(1024) scan_sums(const int32_t* gate, int32_t want, int32_t* sums, int64_t count) {
+  if (*gate != want) return;
   __shared__ int32_t part[1024];
   const int64_t per = (count + 1023) / 1024;
   const int64_t lo = (int64_t)threadIdx.x * per, hi = min(count, lo + per);
@@ -2945,14 +2953,16 @@ __global__ void __launch_bounds__(1024) scan_sums(int32_t* sums, int64_t count) 
   }
 }
 
-__global__ void scan_add(int32_t* a, int64_t len, const int32_t* sums) {
+__global__ void scan_add(const int32_t* gate, int32_t want, int32_t* a, int64_t len, const int32_t* sums) {
+  if (*gate != want) return;
   const int64_t tile = blockIdx.x;
   const int32_t pre = sums[tile];
   if (pre == 0) return;
   for (int64_t i = tile * kScanTile + threadIdx.x; i < min(len, (tile + 1) * kScanTile); i += blockDim.x) a[i] += pre;
 }
 
-__global__ void copy_i32(int32_t* dst, const int32_t* src, int64_t count) {
+__global__ void copy_i32(const int32_t* gate, int32_t* dst, const int32_t* src, int64_t count) {
+  if (*gate != kBuildAtomic) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
 }
@@ -2962,8 +2972,9 @@ __global__ void copy_i32(int32_t* dst, const int32_t* src, int64_t count) {
 // fills them in edge order.  The order of the runs inside a row depends on the
 // schedule; the csr_order_* kernels then put every row whose edge indices are
 // out of order in edge order.
-__global__ void csr_scatter(int32_t n, int64_t m, const int32_t* __restrict__ key, const int32_t* __restrict__ other,
-                            int32_t* cursor, int32_t* col, int32_t* ids) {
+__global__ void csr_scatter(const int32_t* gate, int32_t n, int64_t m, const int32_t* __restrict__ key,
+                            const int32_t* __restrict__ other, int32_t* cursor, int32_t* col, int32_t* ids) {
+  if (*gate != kBuildAtomic) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t w0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); w0 < m; w0 += stride) {
@@ -3038,8 +3049,9 @@ __device__ __forceinline__ void order_short_row(int32_t b, int32_t d, int32_t* c
 // front of `lists` (count counts[0]), longer ones to its back (n entries,
 // count counts[1]); both counts start at zero.  Waves step over the rows in
 // grid strides (the launch grid is capped).
-__global__ void csr_order_rows(int32_t n, const int32_t* __restrict__ row_ptr, int32_t* col,
+__global__ void csr_order_rows(const int32_t* gate, int32_t n, const int32_t* __restrict__ row_ptr, int32_t* col,
                                const int32_t* __restrict__ ids, int32_t* lists, int32_t* counts) {
+  if (*gate != kBuildAtomic) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); r0 < n; r0 += stride) {
@@ -3067,8 +3079,10 @@ __global__ void csr_order_rows(int32_t n, const int32_t* __restrict__ row_ptr, i
 // One wave per listed row of kOrderShort+1..64 edges: lane l holds entry l;
 // unless the edge indices ascend, each lane counts the lanes with a smaller
 // one and writes its column there.
-__global__ void csr_order_mid(const int32_t* __restrict__ row_ptr, int32_t* col, const int32_t* __restrict__ ids,
-                              const int32_t* __restrict__ lists, const int32_t* __restrict__ counts) {
+__global__ void csr_order_mid(const int32_t* gate, const int32_t* __restrict__ row_ptr, int32_t* col,
+                              const int32_t* __restrict__ ids, const int32_t* __restrict__ lists,
+                              const int32_t* __restrict__ counts) {
+  if (*gate != kBuildAtomic) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
@@ -3160,8 +3174,9 @@ __device__ void order_lds_chunk(int32_t* se, int32_t* so, int32_t* E, int32_t* O
 // kOrderChunk entries, else chunks sorted in LDS and merged by steps over the
 // row in global memory (the row's edge indices are scratch).
 __global__ void __launch_bounds__(kOrderThreads)
-    csr_order_long(int32_t n, const int32_t* __restrict__ row_ptr, int32_t* col, int32_t* ids,
+    csr_order_long(const int32_t* gate, int32_t n, const int32_t* __restrict__ row_ptr, int32_t* col, int32_t* ids,
                    const int32_t* __restrict__ lists, const int32_t* __restrict__ counts) {
+  if (*gate != kBuildAtomic) return;
   __shared__ int32_t se[kOrderChunk];
   __shared__ int32_t so[kOrderChunk];
   const int32_t cnt = counts[1];
@@ -3191,6 +3206,178 @@ __global__ void __launch_bounds__(kOrderThreads)
   }
 }
 
+// Picks the build path from 1024 evenly spaced pairs of neighbouring edges:
+// when most pairs differ in key, runs of equal keys are short and every edge
+// would take its own atomic, so the radix sort (bandwidth-bound) is taken.
+constexpr int64_t kRadixMinEdges = 1 << 16;
+__global__ void __launch_bounds__(1024) csr_pick(int64_t m, const int32_t* __restrict__ key, int32_t* mode) {
+  __shared__ uint32_t s_diff;
+  if (threadIdx.x == 0) s_diff = 0;
+  __syncthreads();
+  uint32_t d = 0;
+  if (m >= kRadixMinEdges) {
+    const int64_t i = (m - 1) * (int64_t)threadIdx.x / 1024;
+    d = key[i] != key[i + 1] ? 1u : 0u;
+  }
+  d = wave_sum_u32(d);
+  if ((threadIdx.x & (kWave - 1)) == 0 && d) atomicAdd(&s_diff, d);
+  __syncthreads();
+  if (threadIdx.x == 0) *mode = 2 * s_diff > 1024 ? kBuildRadix : kBuildAtomic;
+}
+
+// Radix path: a least-significant-digit radix sort of (key - 1, other - 1)
+// pairs by key, stable in every pass, so each row lists its columns in edge
+// order; an edge with an endpoint outside 1..n gets key n and sorts last.
+// Digits of up to kRadixMaxBits bits; a tile of kRadixTile edges per
+// workgroup, kRadixSub consecutive ones per wave.
+constexpr int kRadixMaxBits = 9;
+constexpr int kRadixBins = 1 << kRadixMaxBits;
+constexpr int kRadixWaves = 16;
+constexpr int kRadixThreads = kRadixWaves * kWave;
+constexpr int kRadixSub = 512;
+constexpr int kRadixTile = kRadixWaves * kRadixSub;
+
+// Key of edge i (0-based; n for an edge outside 1..n, which also marks status).
+__device__ __forceinline__ int32_t radix_key_in(int32_t n, int64_t i, const int32_t* key, const int32_t* other,
+                                                const int32_t* kin, int32_t* status) {
+  if (kin) return kin[i];
+  const int32_t k = key[i], o = other[i];
+  const bool ok = k >= 1 && k <= n && o >= 1 && o <= n;
+  if (!ok && status) __hip_atomic_store(status, (int32_t)MAP_ERANGE_DEV, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return ok ? k - 1 : n;
+}
+
+// Per tile, the count of each digit value: hist[digit * tiles + tile].
+__global__ void __launch_bounds__(kRadixThreads)
+    radix_count(const int32_t* gate, int32_t n, int64_t m, const int32_t* __restrict__ key,
+                const int32_t* __restrict__ other, const int32_t* __restrict__ kin, int shift, int bits, int64_t tiles,
+                int32_t* hist, int32_t* status) {
+  if (*gate != kBuildRadix) return;
+  __shared__ uint32_t h[kRadixBins];
+  const uint32_t mask = (1u << bits) - 1u;
+  for (int i = threadIdx.x; i <= (int)mask; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const int64_t t0 = (int64_t)blockIdx.x * kRadixTile, t1 = min(m, t0 + kRadixTile);
+  for (int64_t i = t0 + threadIdx.x; i < t1; i += blockDim.x)
+    atomicAdd(&h[((uint32_t)radix_key_in(n, i, key, other, kin, status) >> shift) & mask], 1u);
+  __syncthreads();
+  for (int d = threadIdx.x; d <= (int)mask; d += blockDim.x) hist[(int64_t)d * tiles + blockIdx.x] = (int32_t)h[d];
+}
+
+// Stable scatter of one pass.  hist holds the inclusive scan of the counts
+// (digit-major), so a tile's first slot for digit d is hist[d][tile] minus
+// the tile's own count of d.  The tile is first sorted by digit in LDS, then
+// written out a digit run at a time (consecutive threads, consecutive slots).
+// Inside the tile the waves take their sub-ranges in order (per-wave counts,
+// summed over the waves before), and a wave walks its sub-range 64 edges at a
+// time: the lanes that share a digit (found bit by bit with ballots) take
+// consecutive places in lane order, and the lowest of them advances the
+// wave's cursor for that digit.
+__global__ void __launch_bounds__(kRadixThreads)
+    radix_scatter(const int32_t* gate, int32_t n, int64_t m, const int32_t* __restrict__ key,
+                  const int32_t* __restrict__ other, const int32_t* __restrict__ kin, const int32_t* __restrict__ vin,
+                  int shift, int bits, int64_t tiles, const int32_t* __restrict__ hist, int32_t* kout,
+                  int32_t* vout) {
+  if (*gate != kBuildRadix) return;
+  __shared__ uint32_t off[kRadixWaves][kRadixBins];
+  __shared__ uint32_t loc[kRadixBins];   // first place of each digit in the sorted tile
+  __shared__ uint32_t gpos[kRadixBins];  // its first slot in the output
+  __shared__ int32_t sk[kRadixTile];
+  __shared__ int32_t sv[kRadixTile];
+  const int lane = threadIdx.x & (kWave - 1), wib = threadIdx.x / kWave;
+  const uint32_t mask = (1u << bits) - 1u;
+  for (int i = threadIdx.x; i < kRadixWaves * kRadixBins; i += blockDim.x) off[i / kRadixBins][i % kRadixBins] = 0;
+  __syncthreads();
+  const int64_t t0 = (int64_t)blockIdx.x * kRadixTile;
+  const int32_t cnt = (int32_t)min((int64_t)kRadixTile, m - t0);
+  const int64_t s0 = min(m, t0 + (int64_t)wib * kRadixSub);
+  const int64_t s1 = min(m, s0 + kRadixSub);
+  for (int64_t i = s0 + lane; i < s1; i += kWave)
+    atomicAdd(&off[wib][((uint32_t)radix_key_in(n, i, key, other, kin, nullptr) >> shift) & mask], 1u);
+  __syncthreads();
+  // Per digit: the tile's total (into loc) and each wave's place before the
+  // scan over digits.
+  for (int d = threadIdx.x; d < kRadixBins; d += blockDim.x) {
+    uint32_t run = 0;
+    if (d <= (int)mask) {
+      for (int w = 0; w < kRadixWaves; ++w) {
+        const uint32_t c = off[w][d];
+        off[w][d] = run;
+        run += c;
+      }
+      gpos[d] = (uint32_t)hist[(int64_t)d * tiles + blockIdx.x] - run;
+    }
+    loc[d] = run;
+  }
+  __syncthreads();
+  if (wib == 0) {
+    // Exclusive scan of the digit totals, 8 digits per lane.
+    uint32_t v[kRadixBins / kWave], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kRadixBins / kWave; ++j) {
+      v[j] = loc[lane * (kRadixBins / kWave) + j];
+      sum += v[j];
+    }
+    uint32_t incl = sum;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)incl, o, kWave);
+      if (lane >= o) incl += y;
+    }
+    uint32_t run = incl - sum;
+#pragma unroll
+    for (int j = 0; j < kRadixBins / kWave; ++j) {
+      loc[lane * (kRadixBins / kWave) + j] = run;
+      run += v[j];
+    }
+  }
+  __syncthreads();
+  const unsigned long long below = lane ? (~0ull >> (kWave - lane)) : 0ull;
+  for (int64_t i0 = s0; i0 < s1; i0 += kWave) {
+    const int64_t i = i0 + lane;
+    const bool ok = i < s1;
+    int32_t kk = 0, vv = 0;
+    if (ok) {
+      kk = radix_key_in(n, i, key, other, kin, nullptr);
+      vv = vin ? vin[i] : other[i] - 1;
+    }
+    const uint32_t d = ((uint32_t)kk >> shift) & mask;
+    unsigned long long peers = __ballot(ok);
+    for (int bit = 0; bit < bits; ++bit) {
+      const unsigned long long one = __ballot(ok && ((d >> bit) & 1u));
+      peers &= ((d >> bit) & 1u) ? one : ~one;
+    }
+    const uint32_t r = (uint32_t)__popcll(peers & below);
+    if (ok) {
+      const uint32_t lp = loc[d] + off[wib][d] + r;
+      sk[lp] = kk;
+      sv[lp] = vv;
+    }
+    // Every lane has read off[wib][d] above (the wave's LDS operations
+    // complete in order) before the group's lowest lane advances it.
+    if (ok && r == 0) off[wib][d] += (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
+    const int32_t kk = sk[j];
+    const uint32_t d = ((uint32_t)kk >> shift) & mask;
+    const uint32_t pos = gpos[d] + ((uint32_t)j - loc[d]);
+    kout[pos] = kk;
+    vout[pos] = sv[j];
+  }
+}
+
+// Row pointers from the sorted keys: the rows (key of edge i-1, key of edge
+// i] start at edge i (before the first edge: -1; after the last: n).
+__global__ void radix_row_ptr(const int32_t* gate, int32_t n, int64_t m, const int32_t* __restrict__ ks,
+                              int32_t* row_ptr) {
+  if (*gate != kBuildRadix) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= m; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t prev = i == 0 ? -1 : (int64_t)ks[i - 1];
+    const int64_t cur = i == m ? (int64_t)n : min((int64_t)ks[i], (int64_t)n);
+    for (int64_t r = prev + 1; r <= cur; ++r) row_ptr[r] = (int32_t)i;
+  }
+}
+
 // ------------------------------------------------------------------- host --
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -3199,6 +3386,7 @@ bool sizes_ok(int32_t n, int64_t m) { return n >= 1 && n <= 0x7ffffffe && m >= 0
 
 struct Layout {
   size_t ctrl, pv, accw, front0, front1, mark, aux, chg, accb, parent, cursor, sums, counts, ids, total;
+  size_t rk[2], rv[2], rhist, rsums;  // CSR build, radix path (rk[0] shares the atomic path's ids)
   int64_t words;  // 32-bit words of one vertex bitmap
 };
 
@@ -3239,10 +3427,24 @@ Layout layout(int32_t n, int64_t m = 0) {
   off += align256(((size_t)n + 1) * 4);
   L.sums = off;
   off += align256((((size_t)n + 1 + kScanTile - 1) / kScanTile + 1) * 4);
-  L.counts = off;
+  L.counts = off;  // two list counts, then the build path
   off += 256;
-  L.ids = off;  // edge index of every CSR slot
-  off += align256((size_t)(m > 0 ? m : 0) * 4);
+  const size_t per_edge = align256((size_t)(m > 0 ? m : 0) * 4);
+  L.ids = off;  // edge index of every CSR slot (atomic path)
+  L.rk[0] = off;
+  off += per_edge;
+  L.rv[0] = off;
+  off += per_edge;
+  L.rk[1] = off;
+  off += per_edge;
+  L.rv[1] = off;
+  off += per_edge;
+  const int64_t rtiles = ((m > 0 ? m : 0) + kRadixTile - 1) / kRadixTile;
+  const int64_t rlen = (int64_t)kRadixBins * rtiles;
+  L.rhist = off;
+  off += align256((size_t)rlen * 4);
+  L.rsums = off;
+  off += align256(((size_t)(rlen + kScanTile - 1) / kScanTile + 1) * 4);
   size_t end_build = off;
   L.total = end_loop > end_build ? end_loop : end_build;
   return L;
@@ -3325,30 +3527,79 @@ inline unsigned grid_for(int64_t work, int threads) {
   return (unsigned)g;
 }
 
+// Digit width and pass count of the radix path: keys 0..n (n: an edge outside
+// 1..n) in passes of at most kRadixMaxBits bits.
+static void radix_plan(int32_t n, int* passes, int* bits) {
+  int k = 1;
+  while (k < 31 && (1ll << k) <= (int64_t)n) ++k;
+  *passes = (k + kRadixMaxBits - 1) / kRadixMaxBits;
+  *bits = (k + *passes - 1) / *passes;
+}
+
 int build_one(int32_t n, int64_t m, const int32_t* key, const int32_t* other, int32_t* row_ptr, int32_t* col,
               int32_t* status, char* ws, const Layout& L, hipStream_t stream) {
   int32_t* cursor = reinterpret_cast<int32_t*>(ws + L.cursor);
   int32_t* sums = reinterpret_cast<int32_t*>(ws + L.sums);
   int32_t* counts = reinterpret_cast<int32_t*>(ws + L.counts);
+  int32_t* mode = counts + 2;
   int32_t* ids = reinterpret_cast<int32_t*>(ws + L.ids);
   const int64_t len = (int64_t)n + 1;
+  // Path choice (a device word: the host never waits for the device here).
+  hipLaunchKernelGGL(csr_pick, dim3(1), dim3(1024), 0, stream, m, key, mode);
+  // Atomic path: degree histogram, scan, per-row cursors, then row ordering.
   hipLaunchKernelGGL(fill_i32, dim3(grid_for(len, 256)), dim3(256), 0, stream, row_ptr, len, 0);
   if (m > 0)
-    hipLaunchKernelGGL(csr_hist, dim3(grid_for(m, 256)), dim3(256), 0, stream, n, m, key, other, row_ptr, status);
+    hipLaunchKernelGGL(csr_hist, dim3(grid_for(m, 256)), dim3(256), 0, stream, mode, n, m, key, other, row_ptr,
+                       status);
   const int64_t tiles = (len + kScanTile - 1) / kScanTile;
-  hipLaunchKernelGGL(scan_tiles, dim3((unsigned)tiles), dim3(kScanThreads), 0, stream, row_ptr, len, sums);
-  hipLaunchKernelGGL(scan_sums, dim3(1), dim3(1024), 0, stream, sums, tiles);
-  hipLaunchKernelGGL(scan_add, dim3((unsigned)tiles), dim3(256), 0, stream, row_ptr, len, sums);
+  hipLaunchKernelGGL(scan_tiles, dim3((unsigned)tiles), dim3(kScanThreads), 0, stream, mode, kBuildAtomic, row_ptr,
+                     len, sums);
+  hipLaunchKernelGGL(scan_sums, dim3(1), dim3(1024), 0, stream, mode, kBuildAtomic, sums, tiles);
+  hipLaunchKernelGGL(scan_add, dim3((unsigned)tiles), dim3(256), 0, stream, mode, kBuildAtomic, row_ptr, len, sums);
   if (m > 0) {
-    hipLaunchKernelGGL(copy_i32, dim3(grid_for(n, 256)), dim3(256), 0, stream, cursor, row_ptr, (int64_t)n);
+    hipLaunchKernelGGL(copy_i32, dim3(grid_for(n, 256)), dim3(256), 0, stream, mode, cursor, row_ptr, (int64_t)n);
     hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, stream, counts, (int64_t)2, 0);
-    hipLaunchKernelGGL(csr_scatter, dim3(grid_for(m, 256)), dim3(256), 0, stream, n, m, key, other, cursor, col, ids);
+    hipLaunchKernelGGL(csr_scatter, dim3(grid_for(m, 256)), dim3(256), 0, stream, mode, n, m, key, other, cursor, col,
+                       ids);
     // the cursors are spent: their array holds the lists of longer rows
-    hipLaunchKernelGGL(csr_order_rows, dim3(grid_for(n, 256)), dim3(256), 0, stream, n, row_ptr, col, ids, cursor,
-                       counts);
-    hipLaunchKernelGGL(csr_order_mid, dim3(kOrderMidGrid), dim3(256), 0, stream, row_ptr, col, ids, cursor, counts);
-    hipLaunchKernelGGL(csr_order_long, dim3(kOrderLongGrid), dim3(kOrderThreads), 0, stream, n, row_ptr, col, ids,
+    hipLaunchKernelGGL(csr_order_rows, dim3(grid_for(n, 256)), dim3(256), 0, stream, mode, n, row_ptr, col, ids,
                        cursor, counts);
+    hipLaunchKernelGGL(csr_order_mid, dim3(kOrderMidGrid), dim3(256), 0, stream, mode, row_ptr, col, ids, cursor,
+                       counts);
+    hipLaunchKernelGGL(csr_order_long, dim3(kOrderLongGrid), dim3(kOrderThreads), 0, stream, mode, n, row_ptr, col,
+                       ids, cursor, counts);
+  }
+  // Radix path (m >= kRadixMinEdges only): passes from the edge list through
+  // the two scratch pairs; the last pass writes the columns into col.
+  if (m >= kRadixMinEdges) {
+    int passes = 0, bits = 0;
+    radix_plan(n, &passes, &bits);
+    const int64_t rtiles = (m + kRadixTile - 1) / kRadixTile;
+    const int64_t hlen = (int64_t)(1 << bits) * rtiles;
+    const int64_t htiles = (hlen + kScanTile - 1) / kScanTile;
+    int32_t* hist = reinterpret_cast<int32_t*>(ws + L.rhist);
+    int32_t* hsums = reinterpret_cast<int32_t*>(ws + L.rsums);
+    const int32_t* kin = nullptr;
+    const int32_t* vin = nullptr;
+    int32_t* ks = nullptr;
+    for (int p = 0; p < passes; ++p) {
+      const int shift = p * bits;
+      int32_t* kout = reinterpret_cast<int32_t*>(ws + L.rk[p & 1]);
+      int32_t* vout = p + 1 == passes ? col : reinterpret_cast<int32_t*>(ws + L.rv[p & 1]);
+      hipLaunchKernelGGL(radix_count, dim3((unsigned)rtiles), dim3(kRadixThreads), 0, stream, mode, n, m, key, other,
+                         kin, shift, bits, rtiles, hist, status);
+      hipLaunchKernelGGL(scan_tiles, dim3((unsigned)htiles), dim3(kScanThreads), 0, stream, mode, kBuildRadix, hist,
+                         hlen, hsums);
+      hipLaunchKernelGGL(scan_sums, dim3(1), dim3(1024), 0, stream, mode, kBuildRadix, hsums, htiles);
+      hipLaunchKernelGGL(scan_add, dim3((unsigned)htiles), dim3(256), 0, stream, mode, kBuildRadix, hist, hlen,
+                         hsums);
+      hipLaunchKernelGGL(radix_scatter, dim3((unsigned)rtiles), dim3(kRadixThreads), 0, stream, mode, n, m, key,
+                         other, kin, vin, shift, bits, rtiles, hist, kout, vout);
+      kin = kout;
+      vin = vout;
+      ks = kout;
+    }
+    hipLaunchKernelGGL(radix_row_ptr, dim3(grid_for(m + 1, 256)), dim3(256), 0, stream, mode, n, m, ks, row_ptr);
   }
   return hipGetLastError() == hipSuccess ? MAP_OK : MAP_EDEVICE;
 }

@@ -428,12 +428,13 @@ def _grouped(rng, n, max_deg, m_cap=None):
     return src, dst
 
 
-@pytest.mark.parametrize("case", ["random", "grouped", "hub", "ragged", "invalid"])
+@pytest.mark.parametrize("case", ["random", "grouped", "hub", "ragged", "invalid", "invalid_random"])
 def test_csr_build_key_runs(mc, case):
     """Edges with equal keys share one atomic per run of a wave: runs that
     cross wave boundaries, runs broken by out-of-range edges, lists in random
     order, a vertex whose edges fill many waves, a ragged tail."""
-    rng = np.random.default_rng({"random": 11, "grouped": 12, "hub": 13, "ragged": 14, "invalid": 15}[case])
+    rng = np.random.default_rng({"random": 11, "grouped": 12, "hub": 13, "ragged": 14, "invalid": 15,
+                                 "invalid_random": 16}[case])
     n = 4000
     if case == "random":
         src = rng.integers(1, n + 1, 50_000).astype(np.int32)
@@ -447,6 +448,14 @@ def test_csr_build_key_runs(mc, case):
         dst = np.concatenate([dst[:5000], rng.integers(1, n + 1, 70_000).astype(np.int32), dst[5000:]])
     elif case == "ragged":
         src, dst = _grouped(rng, n, 90, m_cap=64 * 1000 + 37)
+    elif case == "invalid_random":
+        # shuffled (the radix path), with edges outside 1..n at either end
+        src = rng.integers(1, n + 1, 90_000).astype(np.int32)
+        dst = rng.integers(1, n + 1, 90_000).astype(np.int32)
+        bad = rng.choice(len(src), 300, replace=False)
+        src[bad[:100]] = n + 1
+        dst[bad[100:200]] = 0
+        src[bad[200:]] = -5
     else:
         src, dst = _grouped(rng, n, 150)
         bad = rng.choice(len(src), 300, replace=False)
@@ -456,7 +465,7 @@ def test_csr_build_key_runs(mc, case):
     print("csr runs", case, "n", n, "m", len(src), flush=True)
     csr = mc.build_csr(n, src, dst)
     status = int(csr.status.item())
-    assert status == (mc.MAP_ERANGE_DEV if case == "invalid" else 0)
+    assert status == (mc.MAP_ERANGE_DEV if case.startswith("invalid") else 0)
     _check_csr(csr, n, src, dst)
 
 
