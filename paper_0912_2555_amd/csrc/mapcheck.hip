@@ -3230,11 +3230,11 @@ __global__ void __launch_bounds__(1024) csr_pick(int64_t m, const int32_t* __res
 // order; an edge with an endpoint outside 1..n gets key n and sorts last.
 // Digits of up to kRadixMaxBits bits; a tile of kRadixTile edges per
 // workgroup, kRadixSub consecutive ones per wave.
-constexpr int kRadixMaxBits = 9;
+constexpr int kRadixMaxBits = 7;
 constexpr int kRadixBins = 1 << kRadixMaxBits;
-constexpr int kRadixWaves = 16;
+constexpr int kRadixWaves = 8;
 constexpr int kRadixThreads = kRadixWaves * kWave;
-constexpr int kRadixSub = 512;
+constexpr int kRadixSub = 1024;
 constexpr int kRadixTile = kRadixWaves * kRadixSub;
 
 // Key of edge i (0-based; n for an edge outside 1..n, which also marks status).
@@ -3258,8 +3258,16 @@ __global__ void __launch_bounds__(kRadixThreads)
   for (int i = threadIdx.x; i <= (int)mask; i += blockDim.x) h[i] = 0;
   __syncthreads();
   const int64_t t0 = (int64_t)blockIdx.x * kRadixTile, t1 = min(m, t0 + kRadixTile);
-  for (int64_t i = t0 + threadIdx.x; i < t1; i += blockDim.x)
-    atomicAdd(&h[((uint32_t)radix_key_in(n, i, key, other, kin, status) >> shift) & mask], 1u);
+  constexpr int kPer = kRadixTile / kRadixThreads;
+  int32_t kk[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {  // every load of the thread in flight together
+    const int64_t i = t0 + threadIdx.x + (int64_t)u * kRadixThreads;
+    kk[u] = i < t1 ? radix_key_in(n, i, key, other, kin, status) : -1;
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u)
+    if (kk[u] >= 0) atomicAdd(&h[((uint32_t)kk[u] >> shift) & mask], 1u);
   __syncthreads();
   for (int d = threadIdx.x; d <= (int)mask; d += blockDim.x) hist[(int64_t)d * tiles + blockIdx.x] = (int32_t)h[d];
 }
@@ -3292,8 +3300,22 @@ __global__ void __launch_bounds__(kRadixThreads)
   const int32_t cnt = (int32_t)min((int64_t)kRadixTile, m - t0);
   const int64_t s0 = min(m, t0 + (int64_t)wib * kRadixSub);
   const int64_t s1 = min(m, s0 + kRadixSub);
-  for (int64_t i = s0 + lane; i < s1; i += kWave)
-    atomicAdd(&off[wib][((uint32_t)radix_key_in(n, i, key, other, kin, nullptr) >> shift) & mask], 1u);
+  // The wave's sub-range in registers, every load in flight together: step u
+  // holds edges s0 + 64u + lane.
+  constexpr int kSteps = kRadixSub / kWave;
+  int32_t kr[kSteps], vr[kSteps];
+#pragma unroll
+  for (int u = 0; u < kSteps; ++u) {
+    const int64_t i = s0 + (int64_t)u * kWave + lane;
+    kr[u] = vr[u] = 0;
+    if (i < s1) {
+      kr[u] = radix_key_in(n, i, key, other, kin, nullptr);
+      vr[u] = vin ? vin[i] : other[i] - 1;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kSteps; ++u)
+    if (s0 + (int64_t)u * kWave + lane < s1) atomicAdd(&off[wib][((uint32_t)kr[u] >> shift) & mask], 1u);
   __syncthreads();
   // Per digit: the tile's total (into loc) and each wave's place before the
   // scan over digits.
@@ -3332,14 +3354,10 @@ __global__ void __launch_bounds__(kRadixThreads)
   }
   __syncthreads();
   const unsigned long long below = lane ? (~0ull >> (kWave - lane)) : 0ull;
-  for (int64_t i0 = s0; i0 < s1; i0 += kWave) {
-    const int64_t i = i0 + lane;
-    const bool ok = i < s1;
-    int32_t kk = 0, vv = 0;
-    if (ok) {
-      kk = radix_key_in(n, i, key, other, kin, nullptr);
-      vv = vin ? vin[i] : other[i] - 1;
-    }
+#pragma unroll
+  for (int u = 0; u < kSteps; ++u) {
+    const bool ok = s0 + (int64_t)u * kWave + lane < s1;
+    const int32_t kk = kr[u], vv = vr[u];
     const uint32_t d = ((uint32_t)kk >> shift) & mask;
     unsigned long long peers = __ballot(ok);
     for (int bit = 0; bit < bits; ++bit) {
