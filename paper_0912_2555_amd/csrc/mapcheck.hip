@@ -3209,7 +3209,9 @@ __global__ void __launch_bounds__(kOrderThreads)
 // Picks the build path from 1024 evenly spaced pairs of neighbouring edges:
 // when most pairs differ in key, runs of equal keys are short and every edge
 // would take its own atomic, so the radix sort (bandwidth-bound) is taken.
-constexpr int64_t kRadixMinEdges = 1 << 16;
+// Below kRadixMinEdges edges the radix kernels are not even launched: their
+// twenty-odd launches cost more than the atomics they would save.
+constexpr int64_t kRadixMinEdges = 1 << 20;
 __global__ void __launch_bounds__(1024) csr_pick(int64_t m, const int32_t* __restrict__ key, int32_t* mode) {
   __shared__ uint32_t s_diff;
   if (threadIdx.x == 0) s_diff = 0;

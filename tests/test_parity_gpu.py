@@ -403,8 +403,9 @@ def test_csr_build_row_order_every_length(mc, order):
                100_003]
     n = 5000
     rows = rng.permutation(np.arange(1, n + 1))[:len(lengths)]
+    # shuffled lists of 2^20 edges or more take the radix path, grouped ones the per-row cursors
     key = np.concatenate([np.full(d, r, np.int32) for d, r in zip(lengths, rows)]
-                         + [rng.integers(1, n + 1, 30_000).astype(np.int32)])
+                         + [rng.integers(1, n + 1, 1_000_000).astype(np.int32)])
     other = rng.integers(1, n + 1, len(key)).astype(np.int32)
     perm = rng.permutation(len(key)) if order == "random" else np.argsort(key, kind="stable")
     src, dst = key[perm].copy(), other[perm].copy()
@@ -449,9 +450,9 @@ def test_csr_build_key_runs(mc, case):
     elif case == "ragged":
         src, dst = _grouped(rng, n, 90, m_cap=64 * 1000 + 37)
     elif case == "invalid_random":
-        # shuffled (the radix path), with edges outside 1..n at either end
-        src = rng.integers(1, n + 1, 90_000).astype(np.int32)
-        dst = rng.integers(1, n + 1, 90_000).astype(np.int32)
+        # shuffled and over 2^20 edges (the radix path), with edges outside 1..n at either end
+        src = rng.integers(1, n + 1, 1_100_000).astype(np.int32)
+        dst = rng.integers(1, n + 1, 1_100_000).astype(np.int32)
         bad = rng.choice(len(src), 300, replace=False)
         src[bad[:100]] = n + 1
         dst[bad[100:200]] = 0
@@ -482,18 +483,20 @@ def test_csr_build_grid_stride(mc):
     _check_csr(csr, n, src, dst, orientations=1)
 
 
-def test_csr_build_rows_past_one_grid_pass(mc):
+@pytest.mark.parametrize("order", ["shuffled", "grouped"])
+def test_csr_build_rows_past_one_grid_pass(mc, order):
     """n = 2^25 vertices, more rows than one pass of the capped launch covers
     (65,536 workgroups of 256 threads = 2^24): keys spread over the whole
-    range, many above 2^24, rows of every length class, shuffled."""
+    range, many above 2^24, rows of every length class; shuffled (the radix
+    path) or grouped by key (per-row cursors and row ordering)."""
     rng = np.random.default_rng(17)
     n = 1 << 25
-    key = np.concatenate([rng.integers(1, n + 1, 150_000), rng.integers((1 << 24) + 1, n + 1, 150_000),
+    key = np.concatenate([rng.integers(1, n + 1, 600_000), rng.integers((1 << 24) + 1, n + 1, 600_000),
                           np.full(40, n), np.full(5000, n - 1), np.full(70, 1 << 24), np.full(70, (1 << 24) + 1)])
     other = rng.integers(1, n + 1, len(key))
-    perm = rng.permutation(len(key))
+    perm = rng.permutation(len(key)) if order == "shuffled" else np.argsort(key, kind="stable")
     src, dst = key[perm].astype(np.int32), other[perm].astype(np.int32)
-    print("csr past one grid pass n", n, "m", len(src), flush=True)
+    print("csr past one grid pass", order, "n", n, "m", len(src), flush=True)
     csr = mc.build_csr(n, src, dst)
     assert int(csr.status.item()) == 0
     _check_csr(csr, n, src, dst)
