@@ -99,9 +99,12 @@ extern "C" {
  * search).  A sweep whose previous sweep grew fewer than n/16 rows runs as a
  * push round instead: each row that grew raises its predecessors, read from
  * the transposed CSR, with an atomic max; larger frontiers keep the pull over
- * every row.  The results are the same.  Needs rrow_ptr and rcol (else
- * MAP_EINVAL); MAP_EINVAL with MAP_FLAG_PUSH; ignored with MAP_FLAG_DENSE_ONLY
- * and wherever the filtered sweeps do not run. */
+ * every row.  The results are the same.  A push round costs a chain of
+ * dependent device-scope atomics (tens of microseconds), so it pays on large
+ * graphs (config 3, 134M edges: detect twice as fast) and not on small ones
+ * (a 4M-edge graph forced to stream: 1.6x slower).  Needs rrow_ptr and rcol
+ * (else MAP_EINVAL); MAP_EINVAL with MAP_FLAG_PUSH; ignored with
+ * MAP_FLAG_DENSE_ONLY and wherever the filtered sweeps do not run. */
 #define MAP_FLAG_DIRECTION 0x80u
 
 /* Result of map_propagate / map_detect, written to device memory (32 bytes). */

@@ -1004,45 +1004,100 @@ __device__ uint32_t sweep_tile_filt(const LoopArgs& a, const uint8_t* acc, int64
   return grown;
 }
 
+// Lane of this wave whose slice of the combined list holds slot q: the last
+// lane whose first slot is <= q (binary search over the lanes with shuffles;
+// every lane of the wave must call it).
+__device__ __forceinline__ int slot_owner(uint32_t q, uint32_t first) {
+  int lo = 0;
+#pragma unroll
+  for (int step = kWave / 2; step > 0; step >>= 1) {
+    const uint32_t f = (uint32_t)__shfl((int)first, lo + step, kWave);
+    if (f <= q) lo += step;
+  }
+  return lo;
+}
+
 // Filtered stream mode, direction switch (dopt): a sweep whose frontier (the
 // rows that grew in the previous sweep, set in `keep`) is small runs as a
-// push round over the transposed CSR instead of a pull over every row.  Each
-// lane scans one word of `keep` per step and, for every row w set in it,
-// raises each predecessor v with an atomic max of what w sends, behind v's
+// push round over the transposed CSR instead of a pull over every row.  A
+// wave takes 64 words of `keep` at a time and deals their set rows out to its
+// lanes; a lane raises each predecessor v of its row w with an atomic max of
+// what w sends, behind v's
 // own accepting bit and the iteration tag (the reset sweep wrote every row
 // with both, so the words compare by value); a predecessor that grows is set
-// in `mark`.  The result is that of the filtered pull: both fold, into each
-// row, what its grown successors send.  Returns the wave's count of raises
-// that grew a row (a row raised twice counts twice: an upper bound on the
-// next frontier, zero exactly when nothing grew).
+// in `mark`.  A row with more than kPushHub predecessors is queued in LDS and
+// pushed by the whole wave after the step (64 predecessors at a time), so it
+// does not hold up its wave.  The result is that of the filtered pull: both
+// fold, into each row, what its grown successors send.  Returns the wave's
+// count of raises that grew a row (a row raised twice counts twice: an upper
+// bound on the next frontier, zero exactly when nothing grew).
+constexpr int32_t kPushHub = 64;
+__shared__ int32_t g_hubq[kWavesPerBlock][kWave];
+__shared__ uint32_t g_hubn[kWavesPerBlock];
+
+__device__ __forceinline__ bool push_raise(const LoopArgs& a, uint32_t* mark, int32_t v, uint32_t x, uint32_t cur) {
+  if ((uint32_t)v >= (uint32_t)a.n) return false;
+  const uint32_t word = (bit_set(a.accb, (uint32_t)v) ? kAccBit : 0u) | cur | x;
+  const uint32_t old = __hip_atomic_fetch_max(&a.pv[v], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if ((old & a.val_mask) >= x) return false;
+  atomicOr(&mark[v >> 5], 1u << (v & 31));
+  return true;
+}
+
 __device__ __forceinline__ uint32_t push_round_filt(const LoopArgs& a, const uint32_t* keep, uint32_t* mark,
-                                                 uint32_t cur, int64_t gw, int64_t nw, int lane) {
+                                                    uint32_t cur, int64_t gw, int64_t nw, int wib, int lane) {
   g_u32* pvg = (g_u32*)a.pv;
   g_ci32* rrow = (g_ci32*)a.rrow_ptr;
   g_ci32* rcol = (g_ci32*)a.rcol;
   const uint32_t n = (uint32_t)a.n;
   uint32_t grew = 0;
   for (int64_t w0 = gw * kWave; w0 < a.words; w0 += nw * kWave) {
+    if (lane == 0) g_hubn[wib] = 0;
+    wave_lds_sync();
+    // The rows set in the wave's 64 words, dealt out one per lane per step
+    // (rows that grow together sit in the same words).
     const int64_t wi = w0 + lane;
-    uint32_t bits = wi < a.words ? keep[wi] : 0u;
-    while (bits) {
-      const uint32_t w = (uint32_t)(wi << 5) + (uint32_t)__builtin_ctz(bits);
-      bits &= bits - 1u;
-      if (w >= n) break;
+    const uint32_t bits = wi < a.words ? keep[wi] : 0u;
+    const uint32_t c = (uint32_t)__popc(bits);
+    uint32_t incl = c;
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)incl, off, kWave);
+      if (lane >= off) incl += y;
+    }
+    const uint32_t first = incl - c;
+    const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+    for (uint32_t s0 = 0; s0 < total; s0 += kWave) {
+      const uint32_t q = s0 + (uint32_t)lane;
+      const int o = slot_owner(q, first);
+      const uint32_t ob = (uint32_t)__shfl((int)bits, o, kWave);
+      const uint32_t of = (uint32_t)__shfl((int)first, o, kWave);
+      if (q >= total) continue;
+      uint32_t b = ob;
+      for (uint32_t t = of; t < q; ++t) b &= b - 1u;  // drop the owner's set bits before this slot's
+      const uint32_t w = (uint32_t)((w0 + o) << 5) + (uint32_t)__builtin_ctz(b);
+      if (w >= n) continue;
+      const int32_t k0 = rrow[w], k1 = rrow[w + 1];
+      if (k1 - k0 > kPushHub) {
+        const uint32_t hq = atomicAdd(&g_hubn[wib], 1u);
+        if (hq < (uint32_t)kWave) {
+          g_hubq[wib][hq] = (int32_t)w;
+          continue;
+        }
+      }
+      const uint32_t x = sent_word(pvg[w], (int32_t)w, cur, a.val_mask, a.tag_mask);
+      if (!x) continue;
+      for (int32_t k = k0; k < k1; ++k) grew += push_raise(a, mark, rcol[k], x, cur) ? 1u : 0u;
+    }
+    wave_lds_sync();
+    const uint32_t hubs = min(g_hubn[wib], (uint32_t)kWave);
+    for (uint32_t h = 0; h < hubs; ++h) {  // wave-uniform: the whole wave pushes each queued row
+      const uint32_t w = (uint32_t)g_hubq[wib][h];
       const uint32_t x = sent_word(pvg[w], (int32_t)w, cur, a.val_mask, a.tag_mask);
       if (!x) continue;
       const int32_t k1 = rrow[w + 1];
-      for (int32_t k = rrow[w]; k < k1; ++k) {
-        const int32_t v = rcol[k];
-        if ((uint32_t)v >= n) continue;
-        const uint32_t word = (bit_set(a.accb, (uint32_t)v) ? kAccBit : 0u) | cur | x;
-        const uint32_t old = __hip_atomic_fetch_max(&a.pv[v], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((old & a.val_mask) < x) {
-          atomicOr(&mark[v >> 5], 1u << (v & 31));
-          ++grew;
-        }
-      }
+      for (int32_t k = rrow[w] + lane; k < k1; k += kWave) grew += push_raise(a, mark, rcol[k], x, cur) ? 1u : 0u;
     }
+    wave_lds_sync();  // the queue is read before the next step clears it
   }
   return wave_sum_u32(grew);
 }
@@ -1606,7 +1661,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
         // push round), the same in every block
         if (a.dopt && (int64_t)tot * kPushDiv < (int64_t)a.n) {
           const int64_t gw = (int64_t)b * kWavesPerBlock + wib, nw = (int64_t)nb * kWavesPerBlock;
-          c2 = push_round_filt(a, keepb, markb, cur, gw, nw, lane);
+          c2 = push_round_filt(a, keepb, markb, cur, gw, nw, wib, lane);
           PH_MARK(kPhStream);
         } else {
           c2 = sweep_stream_filt<false>(a, acc, W, wib, lane, cur, nullptr, keepb, markb);
@@ -1908,19 +1963,6 @@ __device__ uint32_t lasso_block_sum(uint32_t x) {
 constexpr int kExpandPerLane = 4;
 constexpr uint64_t kUnreached = ~0ull;    // lasso parent word of a vertex not reached
 constexpr uint32_t kNoHit = 0xffffffffu;  // lasso: no edge has entered the target yet
-
-// Lane of this wave whose slice of the combined list holds slot q: the last
-// lane whose first slot is <= q (binary search over the lanes with shuffles;
-// every lane of the wave must call it).
-__device__ __forceinline__ int slot_owner(uint32_t q, uint32_t first) {
-  int lo = 0;
-#pragma unroll
-  for (int step = kWave / 2; step > 0; step >>= 1) {
-    const uint32_t f = (uint32_t)__shfl((int)first, lo + step, kWave);
-    if (f <= q) lo += step;
-  }
-  return lo;
-}
 
 // Appends x[s] for every s with take[s] to frontier F with one counter update
 // for the whole wave; returns the number appended by the wave (wave-uniform).
