@@ -633,6 +633,99 @@ def phase_table(ph, iterations):
     }
 
 
+def single_run(args, workload, steps, warmup):
+    """One graph: the CSR build and map_detect per step, timed as the main line
+    describes; returns the line's fields and the graph (for the CPU leg)."""
+    import torch
+    import paper_0912_2555_amd as mc
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    g = make_graph(workload)
+    n, m = g.n, g.m
+    print(f"[bench] workload {workload} n={n} m={m} |A|={g.n_acc}", file=sys.stderr, flush=True)
+    src = torch.from_numpy(g.src).to(dev)
+    dst = torch.from_numpy(g.dst).to(dev)
+    acc = torch.from_numpy(g.acc).to(dev)
+    ws = mc.workspace(n, m, device=dev)
+    row_ptr = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    col = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    # The transposed CSR is built only where the path reads it (frontier rounds,
+    # the direction switch).
+    # Config 3 runs its filtered sweeps with the direction switch unless told not to.
+    direction = not args.push and (args.direction or (workload == "c3" and not args.pull_only))
+    need_t = args.push or direction
+    rrow_ptr = torch.empty(n + 1, dtype=torch.int32, device=dev) if need_t else None
+    rcol = torch.empty(max(m, 1), dtype=torch.int32, device=dev) if need_t else None
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    res = mc.new_result(dev)
+    stream = torch.cuda.current_stream()
+    flags = mc.MAP_FLAG_NO_TRACE_DIGEST | (mc.MAP_FLAG_SYNC_SWEEPS if args.sync_sweeps else 0) | \
+        (mc.MAP_FLAG_STREAM if args.stream else 0) | (mc.MAP_FLAG_PUSH if args.push else 0) | \
+        (mc.MAP_FLAG_DIRECTION if direction else 0)
+
+    def step(ev=None):
+        rc = mc.map_build_csr(n, src, dst, row_ptr, col, rrow_ptr, rcol, status, ws)
+        if rc:
+            raise mc.MapError(rc, "map_build_csr")
+        if ev is not None:
+            ev[0].record(stream)
+        rc = mc.map_detect(n, row_ptr, col, rrow_ptr, rcol, acc, res, None, None, 0, flags, ws)
+        if rc:
+            raise mc.MapError(rc, "map_detect")
+        if ev is not None:
+            ev[1].record(stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(events[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    r = mc.Result.from_tensor(res)
+    if r.status != 0 or int(status.item()) != 0:
+        raise RuntimeError(f"device status {r.status} / build status {int(status.item())}")
+    ms_step = (t1 - t0) * 1e3 / steps
+    detect_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    k = r.iterations
+    gteps = k * m / (ms_step * 1e-3) / 1e9
+    alg_bytes = method_bytes(n, m, k)
+    achieved = alg_bytes / (detect_ms * 1e-3) / 1e9
+    dense_bytes = r.sweeps * sweep_bytes(n, m) + k * 4 * n
+    dense_gbs = dense_bytes / (detect_ms * 1e-3) / 1e9
+    traffic = counted_traffic(workload, flags)
+    gold = golden_for(workload)
+    exact = None
+    if gold is not None:
+        exact = bool((r.found, r.witness, r.iterations, r.accepting_left)
+                     == (gold["found"], gold["witness"], gold["iterations"], gold["accepting_left"]))
+    out = {
+        "metric": METRIC, "value": round(gteps, 4), "unit": "GTEPS", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": WORKLOADS[workload][0], "key": workload, "n": n, "m": m,
+                   "accepting": int(g.n_acc), "parallelism": "single GPU", "flags": flags},
+        "result": {"found": r.found, "witness": r.witness, "iterations": k, "sweeps": r.sweeps,
+                   "accepting_left": r.accepting_left, "matches_oracle_golden": exact},
+        "detect_ms": round(detect_ms, 4), "build_ms": round(ms_step - detect_ms, 4),
+        "gteps_detect": round(k * m / (detect_ms * 1e-3) / 1e9, 4),
+        "gteps_scan": round(r.sweeps * m / (detect_ms * 1e-3) / 1e9, 4),
+        "roofline": {"bound": "hbm", "kernel": "map_loop_kernel", "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "traffic_gbs": round(traffic / (detect_ms * 1e-3) / 1e9, 2) if traffic else None,
+                     "bytes_per_launch": int(alg_bytes), "accounting": "method: K*(4E+8N) per launch",
+                     "dense_equiv": {"achieved": round(dense_gbs, 2), "frac": round(dense_gbs / HBM_PEAK_GBS, 4),
+                                     "bytes_per_launch": int(dense_bytes),
+                                     "accounting": "whole-graph sweeps * (4(N+1)+4E+8N+N/8) + K*4N per launch"}},
+    }
+    return out, g, k
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -649,6 +742,8 @@ def main():
                          "on by default for config 3")
     ap.add_argument("--pull-only", action="store_true", help="config 3 without the direction switch")
     ap.add_argument("--batch-count", type=int, default=4096, help="graphs in the config-4 batch")
+    ap.add_argument("--line-c3", type=int, default=3,
+                    help="timed config-3 steps added to the default config-2B line (0: none)")
     ap.add_argument("--line-batch", type=int, default=512,
                     help="single-graph line: also run the first N config-4 graphs batched vs plain (0: skip)")
     ap.add_argument("--phases", action="store_true",
@@ -690,98 +785,21 @@ def main():
     import torch
     import paper_0912_2555_amd as mc
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    g = make_graph(args.workload)
-    n, m = g.n, g.m
-    print(f"[bench] workload {args.workload} n={n} m={m} |A|={g.n_acc}", file=sys.stderr, flush=True)
-    src = torch.from_numpy(g.src).to(dev)
-    dst = torch.from_numpy(g.dst).to(dev)
-    acc = torch.from_numpy(g.acc).to(dev)
-    ws = mc.workspace(n, m, device=dev)
-    row_ptr = torch.empty(n + 1, dtype=torch.int32, device=dev)
-    col = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
-    # The transposed CSR is built only where the path reads it (frontier rounds,
-    # the direction switch).
-    # Config 3 runs its filtered sweeps with the direction switch unless told not to.
-    direction = not args.push and (args.direction or (args.workload == "c3" and not args.pull_only))
-    need_t = args.push or direction
-    rrow_ptr = torch.empty(n + 1, dtype=torch.int32, device=dev) if need_t else None
-    rcol = torch.empty(max(m, 1), dtype=torch.int32, device=dev) if need_t else None
-    status = torch.zeros(1, dtype=torch.int32, device=dev)
-    res = mc.new_result(dev)
-    stream = torch.cuda.current_stream()
-    flags = mc.MAP_FLAG_NO_TRACE_DIGEST | (mc.MAP_FLAG_SYNC_SWEEPS if args.sync_sweeps else 0) | \
-        (mc.MAP_FLAG_STREAM if args.stream else 0) | (mc.MAP_FLAG_PUSH if args.push else 0) | \
-        (mc.MAP_FLAG_DIRECTION if direction else 0)
-
-    def step(ev=None):
-        rc = mc.map_build_csr(n, src, dst, row_ptr, col, rrow_ptr, rcol, status, ws)
-        if rc:
-            raise mc.MapError(rc, "map_build_csr")
-        if ev is not None:
-            ev[0].record(stream)
-        rc = mc.map_detect(n, row_ptr, col, rrow_ptr, rcol, acc, res, None, None, 0, flags, ws)
-        if rc:
-            raise mc.MapError(rc, "map_detect")
-        if ev is not None:
-            ev[1].record(stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(events[i])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    r = mc.Result.from_tensor(res)
-    if r.status != 0 or int(status.item()) != 0:
-        raise RuntimeError(f"device status {r.status} / build status {int(status.item())}")
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    detect_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
-    k = r.iterations
-    gteps = k * m / (ms_step * 1e-3) / 1e9
-    alg_bytes = method_bytes(n, m, k)
-    achieved = alg_bytes / (detect_ms * 1e-3) / 1e9
-    dense_bytes = r.sweeps * sweep_bytes(n, m) + k * 4 * n
-    dense_gbs = dense_bytes / (detect_ms * 1e-3) / 1e9
-    traffic = counted_traffic(args.workload, flags)
-    gold = golden_for(args.workload)
-    exact = None
-    if gold is not None:
-        exact = bool((r.found, r.witness, r.iterations, r.accepting_left)
-                     == (gold["found"], gold["witness"], gold["iterations"], gold["accepting_left"]))
-    out = {
-        "metric": METRIC, "value": round(gteps, 4), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload][0], "key": args.workload, "n": n, "m": m,
-                   "accepting": int(g.n_acc), "parallelism": "single GPU", "flags": flags},
-        "result": {"found": r.found, "witness": r.witness, "iterations": k, "sweeps": r.sweeps,
-                   "accepting_left": r.accepting_left, "matches_oracle_golden": exact},
-        "detect_ms": round(detect_ms, 4), "build_ms": round(ms_step - detect_ms, 4),
-        "gteps_detect": round(k * m / (detect_ms * 1e-3) / 1e9, 4),
-        "gteps_scan": round(r.sweeps * m / (detect_ms * 1e-3) / 1e9, 4),
-        "roofline": {"bound": "hbm", "kernel": "map_loop_kernel", "achieved": round(achieved, 2),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "traffic_gbs": round(traffic / (detect_ms * 1e-3) / 1e9, 2) if traffic else None,
-                     "bytes_per_launch": int(alg_bytes), "accounting": "method: K*(4E+8N) per launch",
-                     "dense_equiv": {"achieved": round(dense_gbs, 2), "frac": round(dense_gbs / HBM_PEAK_GBS, 4),
-                                     "bytes_per_launch": int(dense_bytes),
-                                     "accounting": "whole-graph sweeps * (4(N+1)+4E+8N+N/8) + K*4N per launch"}},
-    }
+    out, g, k = single_run(args, args.workload, args.steps, args.warmup)
     if args.phases:
         out["phases"] = phase_table(mc.phase_counters(), k)
     if args.line_batch > 0:
         torch.cuda.synchronize()
-        del ws, row_ptr, col, src, dst
         torch.cuda.empty_cache()
         out["batched"] = batch_run(args, args.line_batch, capture=False)
+    if args.line_c3 > 0 and args.workload == "c2B" and not args.phases:
+        # Config 3 (both CSRs built, filtered sweeps with the direction switch)
+        # beside the headline config-2B figure.
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        c3, _, _ = single_run(args, "c3", args.line_c3, 1)
+        out["config3"] = {key: c3[key] for key in ("value", "unit", "steps", "ms_per_step", "detect_ms", "build_ms",
+                                                   "gteps_detect", "config", "result", "roofline")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, args.workload, args.cpu_budget)
     print(json.dumps(out), flush=True)
