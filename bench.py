@@ -50,6 +50,8 @@ WORKLOADS = {
     "c1a": ("config 1: N=10,000 uniform digraph, out-degree U{1..4}, 5% accepting", "config1", False),
     "c1b": ("config 1 DAG instance: high->low edges of the config-1 draw", "config1", True),
     "c3": ("config 3: N=2^25 DAG, ~134M edges, 0.1% accepting, no accepting cycle", "config3", None),
+    "c3lit": ("config 3, literal reading: the config-1 generator at N=2^25 keeping edges with s > d (a DAG, "
+              "~42M edges), 5% accepting, no accepting cycle", "config1lit", None),
     "c5": ("config 5: Poisson stream of config-1 DAG queries, N log-uniform in [1e4,4e6], accepting ratio "
            "U[0.1%,5%], odd ones planted; continuous batching on one persistent engine under a 32 GiB HBM budget "
            "vs a serial plain loop",
@@ -75,6 +77,8 @@ def make_graph(key):
         return synth.config2(planted=flag)
     if fn == "config1":
         return synth.config1(dag=flag)
+    if fn == "config1lit":
+        return synth.config1(seed=3, n=1 << 25, dag=True)
     return synth.config3()
 
 
@@ -651,8 +655,8 @@ def single_run(args, workload, steps, warmup):
     col = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
     # The transposed CSR is built only where the path reads it (frontier rounds,
     # the direction switch).
-    # Config 3 runs its filtered sweeps with the direction switch unless told not to.
-    direction = not args.push and (args.direction or (workload == "c3" and not args.pull_only))
+    # Config 3 (both readings) runs its filtered sweeps with the direction switch unless told not to.
+    direction = not args.push and (args.direction or (workload in ("c3", "c3lit") and not args.pull_only))
     need_t = args.push or direction
     rrow_ptr = torch.empty(n + 1, dtype=torch.int32, device=dev) if need_t else None
     rcol = torch.empty(max(m, 1), dtype=torch.int32, device=dev) if need_t else None

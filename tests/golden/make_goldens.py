@@ -3,7 +3,7 @@
 Calls only the CPU oracle and the seeded generators; nothing here touches the
 HIP library.  Run from the repository root:
 
-    python tests/golden/make_goldens.py [config2|config3|config4|all]
+    python tests/golden/make_goldens.py [config2|config3|config3lit|config4|all]
 
 Each record holds the verdict (found, witness, K), the accepting count at
 exit, the per-iteration |Del_k| list and the per-iteration map digests
@@ -66,6 +66,10 @@ def main(which):
         data["c2A"] = record(synth.config2(planted=True), "config 2 variant A (planted accepting 64-cycle)")
     if which in ("config3", "all"):
         data["c3"] = record(synth.config3(), "config 3 (2^25-vertex DAG, 0.1% accepting)")
+    if which in ("config3lit", "all"):
+        data["c3lit"] = record(synth.config1(seed=3, n=1 << 25, dag=True),
+                               "config 3, literal reading (the config-1 generator at 2^25 vertices, edges "
+                               "with s > d: a DAG of about 1.25 edges per vertex, 5% accepting)")
     with open(OUT, "w") as f:
         json.dump(data, f, indent=1)
     if which in ("config4", "all"):

@@ -566,6 +566,28 @@ def test_config2_full_size(mc, key, planted):
     assert np.array_equal(got.cpu().numpy(), want)
 
 
+@pytest.mark.parametrize("direction", [False, True], ids=["pull", "direction-switch"])
+def test_config3_literal_full_size(mc, direction):
+    """Config 3's literal reading: the config-1 generator at 2^25 vertices with
+    the edges s > d kept (a DAG of about 42M edges, 5% accepting), against the
+    oracle's golden; with filtered pull sweeps and with the direction switch."""
+    import hashlib
+    g = synth.config1(seed=3, n=1 << 25, dag=True)
+    gold = _golden("c3lit")
+    assert g.n == gold["n"] and g.m == gold["m"]
+    say("full-size detect", g.name, "m", g.m, "direction", direction)
+    csr = mc.build_csr(g.n, g.src, g.dst, transposed=direction)
+    out = mc.detect(csr, g.acc, trace_cap=gold["iterations"] + 1,
+                    flags=mc.MAP_FLAG_DIRECTION if direction else 0)
+    r = out.result
+    assert r.status == 0
+    assert r.verdict == (gold["found"], gold["witness"], gold["iterations"])
+    assert r.accepting_left == gold["accepting_left"]
+    assert [int(x) for x in out.trace[:, 0]] == gold["dels"]
+    dig = out.trace[:, 2].astype("<u8")
+    assert hashlib.sha256(dig.tobytes()).hexdigest() == gold["digest_sha256"]
+
+
 def test_config3_full_size(mc):
     g = synth.config3()
     csr, _ = _check_golden(mc, g, _golden("c3"))
