@@ -141,9 +141,12 @@ size_t map_workspace_bytes(int32_t n, int64_t m, uint32_t flags);
  *   status     device int32 out: MAP_OK, or MAP_ERANGE_DEV if an id lies
  *              outside 1..n (the CSR contents are then unspecified).
  * Duplicate edges and self-loops are kept.  The columns of each row follow
- * the order of their edges in src/dst (a stable counting sort by key), so the
- * CSR is the same on every run.  The workspace holds a per-edge scratch of 4m
- * bytes beside the per-vertex arrays.
+ * the order of their edges in src/dst, so the CSR is the same on every run.
+ * Each orientation is built by one of two paths, chosen on the device from a
+ * sample of neighbouring edges: per-row cursors (one atomic per run of equal
+ * keys) with a pass that orders the rows, when the list is mostly grouped by
+ * key; otherwise a stable radix sort by key (from 2^20 edges).  The workspace
+ * holds four per-edge int32 arrays (16m bytes) beside the per-vertex arrays.
  */
 int map_build_csr(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t *row_ptr,
                   int32_t *col, int32_t *rrow_ptr, int32_t *rcol, int32_t *status, void *ws,

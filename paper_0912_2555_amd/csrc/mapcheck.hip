@@ -11,15 +11,22 @@
 // reaches the same vector; only the sweep count depends on the schedule.
 //
 // Device data layout (workspace):
-//   ctrl   control block: grid-barrier counters and per-epoch reduction slots;
+//   ctrl   control block: grid-barrier counters, per-epoch reduction slots,
+//          the asynchronous change counter and quiet reports, and the
+//          iteration-tag epoch kept across calls;
 //   pv     uint32[n]: bit 31 = vertex is accepting in the current iteration,
-//          bit 30 = parity of the iteration that wrote the word (n < 2^30),
-//          low bits = current map value (id, 0 = none);
-//   accw   uint8[n]: working accepting flags, stripped between iterations.
+//          low bits (the bit length of n) = current map value (id, 0 = none),
+//          the bits between = tag of the iteration that wrote the word;
+//   accw   uint8[n]: working accepting flags, stripped between iterations;
+//   frontier lists, change bitmaps and the CSR build's scratch (see layout()).
 //
 // One cooperative persistent kernel runs the whole outer loop (reset, sweeps
 // to the fixpoint, detect, strip, next iteration) with grid barriers between
 // phases; the host enqueues one launch per call and never synchronizes.
+// Sweeps pull over the CSR (staged in LDS where a workgroup's slice fits,
+// streamed otherwise); on large graphs the streamed sweeps can switch to
+// pushing from the rows that grew over the transposed CSR.  The CSR itself is
+// built on the device, by per-row cursors or a radix sort.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1500,7 +1507,7 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
     if (sync && a.push) {
       // Frontier rounds over the transposed CSR: every vertex whose value grew
       // sends its new value to each predecessor with an atomic max on the
-      // packed word (same accepting bit and parity, so the words compare by
+      // packed word (same accepting bit and tag, so the words compare by
       // value); the predecessors that grew form the next frontier.  A grid
       // barrier ends each round and carries the size of the next frontier.
       // The reset gives every row map 0 and puts the accepting rows in the
