@@ -52,7 +52,7 @@ constexpr int kEdgesPerLane = kTileEdges / kWave;
 constexpr int kResRowsPerLane = 4;                     // resident mode: rows per lane
 constexpr int kResWaveRows = kWave * kResRowsPerLane;  // resident mode: rows per wave
 constexpr int kResEdges = 24576;                        // resident mode: CSR edges per block in LDS
-constexpr int kGatherBatch = 12;                        // resident mode: gathers in flight per lane
+constexpr int kGatherBatch = 6;                         // resident mode: gathers in flight per lane
 constexpr int kLocalPasses = 4;                         // resident mode: LDS-only passes after a sweep
 constexpr int kSortSlots = 1024;                        // resident mode: bitonic sort width (>= 64 * kGatherBatch)
 constexpr int kSortPerLane = kSortSlots / kWave;
@@ -276,7 +276,7 @@ __device__ bool grid_sync(Grid<C>& g, uint32_t payload, uint32_t* total) {
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (!ok) st_agent((uint32_t*)&c->abort, 1u);
-    s_total = ok ? ld_agent(&c->payload) : 0u;
+    if (total) s_total = ok ? ld_agent(&c->payload) : 0u;
     s_ok = ok;
   }
   __syncthreads();
@@ -1718,22 +1718,16 @@ __device__ void map_body(const LoopArgs& a, C* c, const int nb, const int b, con
         nz |= mv;
       };
       if (W.resident) {
-        // Every flag of the lane's rows is read before any is cleared, so the
-        // reads overlap (rows that share a map value clear it twice, which is
-        // harmless).
-        uint32_t mvs[kResRowsPerLane];
-        uint8_t fl[kResRowsPerLane];
+        // The flag of every map value is cleared without reading it first: no
+        // load waits here, and the stores complete before the barrier below
+        // (rows that share a map value clear it more than once, harmlessly).
 #pragma unroll
         for (int j = 0; j < kResRowsPerLane; ++j) {
           const int64_t v = W.r0 + lane + j * kWave;
-          mvs[j] = v < W.r1 ? g_lds.res.pv[v - W.rb0] & a.val_mask : 0u;
-          if (v < W.r1) note(v, mvs[j]);
+          const uint32_t mv = v < W.r1 ? g_lds.res.pv[v - W.rb0] & a.val_mask : 0u;
+          if (v < W.r1) note(v, mv);
+          if (mv) acc[mv - 1] = 0;
         }
-#pragma unroll
-        for (int j = 0; j < kResRowsPerLane; ++j) fl[j] = mvs[j] ? acc[mvs[j] - 1] : (uint8_t)0;
-#pragma unroll
-        for (int j = 0; j < kResRowsPerLane; ++j)
-          if (fl[j]) acc[mvs[j] - 1] = 0;
       } else {
         for_own_rows(a, W, lane, [&](int64_t v, uint32_t x) {
           const uint32_t mv = x & a.val_mask;
