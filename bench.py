@@ -179,7 +179,9 @@ def batch_run(args, count, capture=True):
         g = synth.config4(i)
         if ws is None or ws.numel() < mc.map_workspace_bytes(g.n, g.m):
             ws = mc.workspace(max(g.n, 1 << 20), max(g.m, 1 << 22), device=dev)
-        csrs.append(mc.build_csr(g.n, g.src, g.dst, transposed=False, ws=ws))
+        # Both CSRs: the transposed one is read only by the direction-switch
+        # option rules the tuner tries.
+        csrs.append(mc.build_csr(g.n, g.src, g.dst, transposed=True, ws=ws))
         accs.append(torch.from_numpy(g.acc).to(dev))
         ns.append(g.n)
         ms.append(g.m)

@@ -299,16 +299,27 @@ typedef struct map_graph_desc {
   const int32_t *row_ptr;     /* device pull CSR from map_build_csr: int32[n+1] */
   const int32_t *col;         /* device int32[m] */
   const uint8_t *accepting0;  /* device uint8[n]: A_1, not modified */
+  const int32_t *rrow_ptr;    /* device transposed CSR (successors) from map_build_csr, or NULL: int32[n+1] */
+  const int32_t *rcol;        /* device int32[m], or NULL; read only with MAP_GRAPH_DIRECTION */
 } map_graph_desc;
 
 /* map_graph_desc.options.  Low 16 bits: a row with more edges than this in a
  * staged chunk of a streamed tile (512 edges) is folded by the whole wave
  * instead of its own lane (0 = the default, 64).  MAP_GRAPH_SYNC_SWEEPS and
  * MAP_GRAPH_STREAM apply MAP_FLAG_SYNC_SWEEPS / MAP_FLAG_STREAM to this graph
- * alone.  None of them changes a result. */
+ * alone.  MAP_GRAPH_FILTER runs this graph's gang with filtered stream sweeps
+ * (a barrier after every sweep; a sweep gathers only from rows that grew in
+ * the one before, as map_detect does when no workgroup can stage its rows on
+ * chip); ignored with MAP_FLAG_EARLY.  MAP_GRAPH_DIRECTION, with
+ * MAP_GRAPH_FILTER and the graph's transposed CSR in rrow_ptr / rcol, adds the
+ * direction switch of MAP_FLAG_DIRECTION (a sweep after one that grew fewer
+ * than n / 16 rows runs as push rounds over the transposed CSR); without them
+ * it is ignored.  None of them changes a result. */
 #define MAP_GRAPH_HUB_MASK 0xffff
 #define MAP_GRAPH_SYNC_SWEEPS 0x10000
 #define MAP_GRAPH_STREAM 0x20000
+#define MAP_GRAPH_FILTER 0x40000
+#define MAP_GRAPH_DIRECTION 0x80000
 
 /*
  * Bytes of device workspace for map_detect_batch over `count` graphs whose

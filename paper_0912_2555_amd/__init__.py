@@ -388,9 +388,11 @@ def trim(csr: Csr, accepting=None, ws=None, stream=None, sync: bool = True) -> T
 MAP_GRAPH_HUB_MASK = 0xFFFF
 MAP_GRAPH_SYNC_SWEEPS = 0x10000
 MAP_GRAPH_STREAM = 0x20000
+MAP_GRAPH_FILTER = 0x40000
+MAP_GRAPH_DIRECTION = 0x80000
 GRAPH_DESC = np.dtype([("n", "<i4"), ("options", "<i4"), ("m", "<i8"), ("row_ptr", "<u8"), ("col", "<u8"),
-                       ("accepting0", "<u8")])
-assert GRAPH_DESC.itemsize == 40
+                       ("accepting0", "<u8"), ("rrow_ptr", "<u8"), ("rcol", "<u8")])
+assert GRAPH_DESC.itemsize == 56
 
 
 class Batch:
@@ -398,8 +400,9 @@ class Batch:
 
     ``csrs`` and ``accs`` stay referenced so the device buffers outlive the
     launch.  Graphs are processed in the order given.  ``options`` (one int per
-    graph, map_graph_desc.options) sets a graph's long-row threshold and
-    fixpoint control; None leaves every graph at the defaults.
+    graph, map_graph_desc.options) sets a graph's long-row threshold, fixpoint
+    control, filtered sweeps and direction switch (the last needs the graph's
+    transposed CSR); None leaves every graph at the defaults.
     """
 
     def __init__(self, csrs, accs, gang=None, flags: int = 0, device="cuda", options=None):
@@ -409,7 +412,9 @@ class Batch:
         opts = np.zeros(self.count, np.int64) if options is None else np.asarray(options, np.int64)
         desc = np.zeros(self.count, GRAPH_DESC)
         for i, (c, a) in enumerate(zip(self.csrs, self.accs)):
-            desc[i] = (c.n, int(opts[i]), c.m, c.row_ptr.data_ptr(), c.col.data_ptr(), a.data_ptr())
+            desc[i] = (c.n, int(opts[i]), c.m, c.row_ptr.data_ptr(), c.col.data_ptr(), a.data_ptr(),
+                       c.rrow_ptr.data_ptr() if c.rrow_ptr is not None else 0,
+                       c.rcol.data_ptr() if c.rcol is not None else 0)
         self.desc = torch.from_numpy(desc.view(np.uint8).copy()).to(device)
         self.gang = None if gang is None else torch.as_tensor(np.asarray(gang, np.int32)).to(device)
         self.total_n = int(sum(c.n for c in self.csrs))

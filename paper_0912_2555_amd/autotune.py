@@ -12,13 +12,16 @@ Two knobs per graph class:
   Both kinds of launch can be captured in a HIP graph.
 - the per-graph options (map_graph_desc.options): the fixpoint control of a
   multi-workgroup gang (asynchronous sweeps or a barrier after every sweep),
-  whether its CSR is streamed instead of staged on chip, and the long-row
+  whether its CSR is streamed instead of staged on chip, whether streamed
+  sweeps gather only from rows that grew (filtered sweeps) and switch to push
+  rounds over the transposed CSR on small frontiers, and the long-row
   threshold above which a streamed row is folded by a whole wavefront.  An
   option rule maps a graph's class -- its gang size, n and largest out-degree
   -- to options.
 
 The tuner times the gang policies on the actual batch, then the option rules
-on the fastest gang policy, keeps the fastest pair, and caches it per device
+on the fastest gang policy, then (if a rule won) the gang policies again under
+that rule, keeps the fastest pair, and caches it per device
 and batch shape in a JSON file (``$MAPCHECK_TUNE_CACHE``, default
 ``~/.cache/mapcheck/tune.json``).  No knob changes a result.
 """
@@ -44,6 +47,8 @@ CANDIDATES = (None,
 # map_graph_desc.options bits (include/mapcheck.h)
 GRAPH_SYNC_SWEEPS = 0x10000
 GRAPH_STREAM = 0x20000
+GRAPH_FILTER = 0x40000
+GRAPH_DIRECTION = 0x80000
 HUB_NEVER = 0xFFFF
 # Option rules: name -> options(gang, n, max_degree).
 OPTION_RULES = {
@@ -53,6 +58,12 @@ OPTION_RULES = {
     "stream-single": lambda gang, n, dmax: GRAPH_STREAM if gang == 1 else 0,
     "hub8": lambda gang, n, dmax: 8 if dmax > 8 else 0,
     "hub-never": lambda gang, n, dmax: HUB_NEVER,
+    "filter-gangs": lambda gang, n, dmax: GRAPH_FILTER if gang > 1 else 0,
+    "filter-all": lambda gang, n, dmax: GRAPH_FILTER,
+    # Direction switch (push rounds on small frontiers): needs each graph's
+    # transposed CSR, otherwise the option is ignored.
+    "direction-gangs": lambda gang, n, dmax: GRAPH_FILTER | GRAPH_DIRECTION if gang > 1 else 0,
+    "direction-all": lambda gang, n, dmax: GRAPH_FILTER | GRAPH_DIRECTION,
 }
 
 
@@ -150,8 +161,10 @@ def tune(make_batch, ns, ms, device_name: str, reps: int = 2, use_cache: bool = 
 def tune_knobs(make_batch, ns, ms, dmaxs, device_name: str, reps: int = 2, use_cache: bool = True, log=None,
                gang_candidates=CANDIDATES, rules=tuple(OPTION_RULES)):
     """Both knobs: the gang policy (options at their defaults), then the option
-    rule on the fastest gang policy.  make_batch(gangs, options) builds the
-    batch.  Returns ({"gang": policy, "options": rule}, timings by name)."""
+    rule on the fastest gang policy, then (when a rule other than the default
+    won) the gang policies again under that rule.  make_batch(gangs, options)
+    builds the batch.  Returns ({"gang": policy, "options": rule}, timings by
+    name)."""
     import torch
     key = "knobs|" + _key(device_name, ns, ms) + "|" + str(int(np.max(dmaxs)) if len(dmaxs) else 0)
     path = _cache_path()
@@ -200,6 +213,19 @@ def tune_knobs(make_batch, ns, ms, dmaxs, device_name: str, reps: int = 2, use_c
             log(f"[tune] options {rule}: {t * 1e3:.2f} ms")
         if t < best_t:
             best_rule, best_t = rule, t
+    if best_rule != "default":
+        # The gang policies again, under the chosen option rule (an option such
+        # as the direction switch changes which gang size pays).
+        for cand in gang_candidates:
+            if cand == best_gang:
+                continue
+            g2 = gang_sizes(ns, ms, cand)
+            t = time_batch(g2, graph_options(best_rule, g2, ns, dmaxs))
+            timings["gang:" + policy_name(cand) + "|" + best_rule] = t
+            if log:
+                log(f"[tune] gang {policy_name(cand)} with {best_rule}: {t * 1e3:.2f} ms")
+            if t < best_t:
+                best_gang, best_t = cand, t
     choice = {"gang": best_gang, "options": best_rule}
     if use_cache:
         cache[key] = {"gang": None if best_gang is None else list(best_gang), "options": best_rule,

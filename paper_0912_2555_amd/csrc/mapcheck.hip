@@ -1896,6 +1896,9 @@ __device__ __noinline__ void map_body_gang_sync(const LoopArgs& a, GangCtrl* c, 
 __device__ __noinline__ void map_body_gang_sync_early(const LoopArgs& a, GangCtrl* c, int nb, int rank) {
   map_body<GangCtrl, false, true>(a, c, nb, rank, rank);
 }
+__device__ __noinline__ void map_body_gang_filt(const LoopArgs& a, GangCtrl* c, int nb, int rank) {
+  map_body<GangCtrl, false, false, true>(a, c, nb, rank, rank);
+}
 // One graph solved by a gang, in the fixpoint control and mode its arguments ask
 // for.  MAP_FLAG_EARLY always runs with a grid barrier after every sweep: the
 // asynchronous early body is not built (its builds hung on the device).
@@ -1903,6 +1906,8 @@ __device__ __forceinline__ void map_body_gang(const LoopArgs& a, GangCtrl* c, in
   const bool async = nb > 1 && !a.sync_sweeps && a.tag_mask;
   if (a.early) {
     map_body_gang_sync_early(a, c, nb, rank);
+  } else if (a.filt) {
+    map_body_gang_filt(a, c, nb, rank);
   } else {
     if (async) map_body_gang_async(a, c, nb, rank);
     else map_body_gang_sync(a, c, nb, rank);
@@ -2352,10 +2357,21 @@ aborted:
   if (leader) a.result->status = MAP_EDEVICE;
 }
 
-// Loop arguments of one graph solved by a gang: scratch holds the packed
-// values (4n bytes, 256-aligned) followed by the working accepting flags.
-__device__ LoopArgs gang_args(int32_t n, const int32_t* row_ptr, const int32_t* col, const uint8_t* acc0,
-                              char* scratch, map_result* result, uint32_t flags, int32_t options) {
+// Scratch of one graph of a batch: the packed values (4n bytes), the working
+// accepting flags (n), and with MAP_GRAPH_FILTER the three change bitmaps and
+// the accepting bitmap of the filtered sweeps (ceil(n / 32) words each); every
+// part 256-aligned.
+__host__ __device__ inline int64_t gang_bitmap_bytes(int64_t n) { return ((((n + 31) / 32) * 4) + 255) & ~(int64_t)255; }
+__host__ __device__ inline int64_t gang_scratch_bytes(int64_t n, int32_t options) {
+  n = n < 1 ? 1 : n;
+  const int64_t base = ((n * 4 + 255) & ~(int64_t)255) + ((n + 255) & ~(int64_t)255);
+  return base + ((options & MAP_GRAPH_FILTER) ? 4 * gang_bitmap_bytes(n) : 0);
+}
+
+// Loop arguments of one graph solved by a gang, on its scratch.
+__device__ LoopArgs gang_args(int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* rrow_ptr,
+                              const int32_t* rcol, const uint8_t* acc0, char* scratch, map_result* result,
+                              uint32_t flags, int32_t options) {
   LoopArgs a;
   a.n = n;
   a.ntiles = (int32_t)(((int64_t)n + kTileRows - 1) / kTileRows);
@@ -2380,18 +2396,36 @@ __device__ LoopArgs gang_args(int32_t n, const int32_t* row_ptr, const int32_t* 
   a.push = 0;
   a.early = (flags & MAP_FLAG_EARLY) ? 1 : 0;
   a.rrow_ptr = nullptr;
+  a.rcol = nullptr;
+  a.front[0] = a.front[1] = nullptr;
+  a.mark = nullptr;
   a.chg = nullptr;
   a.accb = nullptr;
   a.words = 0;
   a.filt = 0;
+  a.dopt = 0;
+  if ((options & MAP_GRAPH_FILTER) && !a.early) {
+    // Filtered stream sweeps, a barrier after each (the change bitmaps follow
+    // the working flags).
+    const int64_t off = (((int64_t)n * 4 + 255) & ~(int64_t)255) + (((int64_t)n + 255) & ~(int64_t)255);
+    const int64_t bb = gang_bitmap_bytes(n);
+    a.chg = reinterpret_cast<uint32_t*>(scratch + off);
+    a.accb = reinterpret_cast<uint32_t*>(scratch + off + 3 * bb);
+    a.words = ((int64_t)n + 31) / 32;
+    a.filt = 1;
+    if ((options & MAP_GRAPH_DIRECTION) && rrow_ptr && rcol) {
+      // Direction switch: small frontiers run as push rounds.
+      a.dopt = 1;
+      a.rrow_ptr = rrow_ptr;
+      a.rcol = rcol;
+    }
+  }
   // Per-graph options of a batch (map_graph_desc.options): long-row threshold,
-  // barrier per sweep, streamed CSR.
+  // barrier per sweep, streamed CSR (filtered sweeps and the direction switch
+  // above).
   a.hub = (options & MAP_GRAPH_HUB_MASK) ? (options & MAP_GRAPH_HUB_MASK) : kHubEdges;
   if (options & MAP_GRAPH_SYNC_SWEEPS) a.sync_sweeps = 1;
   if (options & MAP_GRAPH_STREAM) a.force_stream = 1;
-  a.rcol = nullptr;
-  a.front[0] = a.front[1] = nullptr;
-  a.mark = nullptr;
   return a;
 }
 
@@ -2432,7 +2466,8 @@ __global__ void __launch_bounds__(kBlock) map_batch_kernel(BatchArgs ba) {
       continue;
     }
     char* base = ba.scratch + ba.scratch_off[gi];
-    const LoopArgs a = gang_args(d.n, d.row_ptr, d.col, d.accepting0, base, ba.results + gi, ba.flags, d.options);
+    const LoopArgs a = gang_args(d.n, d.row_ptr, d.col, d.rrow_ptr, d.rcol, d.accepting0, base, ba.results + gi,
+                                 ba.flags, d.options);
     map_body_gang(a, ba.gctrl + gi, nb, rank);
   }
 }
@@ -2712,7 +2747,7 @@ __device__ __noinline__ void engine_job(const EngineArgs& ea, int slot, int rank
                         ej.host_edges ? reinterpret_cast<int32_t*>(stage + edge_bytes) : nullptr, g, nb, rank, &bad);
   }
   if (ok && bad == 0) {
-    const LoopArgs a = gang_args(j.n, j.row_ptr, j.col, j.accepting0, sc, res, ea.flags, 0);
+    const LoopArgs a = gang_args(j.n, j.row_ptr, j.col, nullptr, nullptr, j.accepting0, sc, res, ea.flags, 0);
     map_body_gang(a, mcx, nb, rank);
   }
   // Leave the job: release this block's writes, then report (ranks > 0) or
@@ -2838,8 +2873,7 @@ __global__ void __launch_bounds__(1024) batch_plan(int32_t count, const map_grap
     int32_t gsz = gang ? gang[i] : 1;
     gsz = max(1, min(gsz, max_gang));
     si += gsz;
-    const int64_t n = max(graphs[i].n, 1);
-    sb += (int64_t)((n * 4 + 255) & ~255) + (int64_t)((n + 255) & ~255);
+    sb += gang_scratch_bytes(graphs[i].n, graphs[i].options);
   }
   part_i[threadIdx.x] = si;
   part_b[threadIdx.x] = sb;
@@ -2859,8 +2893,7 @@ __global__ void __launch_bounds__(1024) batch_plan(int32_t count, const map_grap
     scratch_off[i] = pb;
     int32_t gsz = gang ? gang[i] : 1;
     pi += max(1, min(gsz, max_gang));
-    const int64_t n = max(graphs[i].n, 1);
-    pb += (int64_t)((n * 4 + 255) & ~255) + (int64_t)((n + 255) & ~255);
+    pb += gang_scratch_bytes(graphs[i].n, graphs[i].options);
   }
   if (threadIdx.x == 1023) {
     item_start[count] = (int32_t)part_i[1023];
@@ -3683,7 +3716,9 @@ BatchLayout batch_layout(int32_t count, int64_t total_n) {
   L.gctrl = off;
   off += (size_t)count * kGangCtrlBytes;
   L.scratch = off;
-  off += (size_t)total_n * 5 + (size_t)count * 512;
+  // Per graph at most gang_scratch_bytes with MAP_GRAPH_FILTER: 5n + 4 ceil(n / 32)
+  // words plus six 256-byte alignments.
+  off += (size_t)total_n * 5 + (size_t)(total_n / 2) + (size_t)count * (2 * 256 + 4 * (4 + 256));
   L.total = off;
   return L;
 }

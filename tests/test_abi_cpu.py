@@ -53,10 +53,13 @@ def test_header_compiles_as_c():
     with tempfile.TemporaryDirectory() as d:
         src = os.path.join(d, "t.c")
         with open(src, "w") as f:
-            f.write('#include "mapcheck.h"\nint main(void){ map_result r; map_job j; map_lasso_result l; '
-                    'map_trim_result t; (void)r; (void)j; (void)l; (void)t; '
+            # Sizes and the descriptor's layout as the Python binding packs them.
+            f.write('#include <stddef.h>\n#include "mapcheck.h"\nint main(void){ map_result r; map_job j; '
+                    'map_lasso_result l; map_trim_result t; (void)r; (void)j; (void)l; (void)t; '
                     'return (int)sizeof(map_result) - 32 + (int)sizeof(map_job) - 72 '
-                    '+ (int)sizeof(map_lasso_result) - 32 + (int)sizeof(map_trim_result) - 16; }\n')
+                    '+ (int)sizeof(map_lasso_result) - 32 + (int)sizeof(map_trim_result) - 16 '
+                    '+ (int)sizeof(map_graph_desc) - 56 + (int)offsetof(map_graph_desc, rrow_ptr) - 40 '
+                    '+ (int)offsetof(map_graph_desc, rcol) - 48; }\n')
         subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
                                "-o", os.path.join(d, "t"), src])
         assert subprocess.call([os.path.join(d, "t")]) == 0

@@ -23,6 +23,11 @@ def test_option_rules():
     assert o("stream-single") == [autotune.GRAPH_STREAM, 0, 0]
     assert o("hub8") == [0, 8, 8]
     assert o("hub-never") == [autotune.HUB_NEVER] * 3
+    assert o("filter-gangs") == [0, autotune.GRAPH_FILTER, autotune.GRAPH_FILTER]
+    assert o("filter-all") == [autotune.GRAPH_FILTER] * 3
+    fd = autotune.GRAPH_FILTER | autotune.GRAPH_DIRECTION
+    assert o("direction-gangs") == [0, fd, fd]
+    assert o("direction-all") == [fd] * 3
     # gangs None: one workgroup per graph
     assert autotune.graph_options("stream-single", None, ns, dmax) == [autotune.GRAPH_STREAM] * 3
 
@@ -36,3 +41,5 @@ def test_option_bits_match_the_header():
     assert int(vals["MAP_GRAPH_SYNC_SWEEPS"], 16) == autotune.GRAPH_SYNC_SWEEPS
     assert int(vals["MAP_GRAPH_STREAM"], 16) == autotune.GRAPH_STREAM
     assert int(vals["MAP_GRAPH_HUB_MASK"], 16) == autotune.HUB_NEVER
+    assert int(vals["MAP_GRAPH_FILTER"], 16) == autotune.GRAPH_FILTER
+    assert int(vals["MAP_GRAPH_DIRECTION"], 16) == autotune.GRAPH_DIRECTION

@@ -33,9 +33,9 @@ def graphs():
     return gs, refs
 
 
-def _check(mc, gs, refs, gang=None, flags=0, order=None, options=None):
+def _check(mc, gs, refs, gang=None, flags=0, order=None, options=None, transposed=False):
     order = list(range(len(gs))) if order is None else order
-    csrs = [mc.build_csr(gs[i].n, gs[i].src, gs[i].dst, transposed=False) for i in order]
+    csrs = [mc.build_csr(gs[i].n, gs[i].src, gs[i].dst, transposed=transposed) for i in order]
     opts = None if options is None else [options[i] for i in order]
     b = mc.Batch(csrs, [gs[i].acc for i in order], gang=gang, flags=flags, options=opts)
     b.launch()
@@ -109,15 +109,20 @@ def _hub_graph():
     return synth.Graph(n=base.n, src=e[:, 0].copy(), dst=e[:, 1].copy(), acc=base.acc, name="c1-hubs")
 
 
-@pytest.mark.parametrize("opt", ["hub1", "hub8", "hub-never", "sync", "stream", "stream+sync+hub16"])
+@pytest.mark.parametrize("opt", ["hub1", "hub8", "hub-never", "sync", "stream", "stream+sync+hub16", "filter",
+                                 "filter+hub8", "direction"])
 def test_batch_per_graph_options(mc, graphs, opt):
-    """Per-graph options (long-row threshold, barrier per sweep, streamed CSR)
-    on every other graph, the hub graph among them: every result exact."""
+    """Per-graph options (long-row threshold, barrier per sweep, streamed CSR,
+    filtered sweeps) on every other graph, the hub graph among them: every
+    result exact."""
     gs, refs = graphs
     gs = gs + [_hub_graph()]
     refs = refs + [oracle.map_detect(gs[-1], mode="desc")]
     o = {"hub1": 1, "hub8": 8, "hub-never": mc.MAP_GRAPH_HUB_MASK, "sync": mc.MAP_GRAPH_SYNC_SWEEPS,
          "stream": mc.MAP_GRAPH_STREAM,
-         "stream+sync+hub16": mc.MAP_GRAPH_STREAM | mc.MAP_GRAPH_SYNC_SWEEPS | 16}[opt]
+         "stream+sync+hub16": mc.MAP_GRAPH_STREAM | mc.MAP_GRAPH_SYNC_SWEEPS | 16,
+         "filter": mc.MAP_GRAPH_FILTER, "filter+hub8": mc.MAP_GRAPH_FILTER | 8,
+         "direction": mc.MAP_GRAPH_FILTER | mc.MAP_GRAPH_DIRECTION}[opt]
     options = [o if i % 2 == 0 or i == len(gs) - 1 else 0 for i in range(len(gs))]
-    _check(mc, gs, refs, gang=[1 if g.n < 20000 else 4 for g in gs], options=options)
+    _check(mc, gs, refs, gang=[1 if g.n < 20000 else 4 for g in gs], options=options,
+           transposed=opt == "direction")

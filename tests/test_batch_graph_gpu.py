@@ -77,7 +77,8 @@ def test_tuned_knobs_exact(mc, batch):
     import torch
     from paper_0912_2555_amd import autotune
     gs, refs = batch
-    csrs = [mc.build_csr(g.n, g.src, g.dst, transposed=False) for g in gs]
+    # Both CSRs, so that the direction-switch rules the tuner tries take effect.
+    csrs = [mc.build_csr(g.n, g.src, g.dst, transposed=True) for g in gs]
     ns, ms = [g.n for g in gs], [g.m for g in gs]
     dmax = [int(np.bincount(g.src).max()) if g.m else 0 for g in gs]
 
