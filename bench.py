@@ -363,20 +363,35 @@ def bench_serve(args):
           flush=True)
 
     budget = 32 << 30
-    with serve.Server(hbm_budget=budget) as srv:
-        warm = queries()[:16]
-        serve.run_stream(warm, qps=1e9, server=srv)             # warm-up
-        # gang policy: each candidate serves a sample of the stream, all at once, on this engine
-        if args.serve_policy == "tune":
-            tsample = queries()[:min(count, 200)]
+    # Engine mode (pull sweeps as map_detect, or filtered sweeps with the
+    # direction switch) and gang policy: each candidate serves a sample of the
+    # stream, all at once, on an engine of that mode.
+    modes = {"pull": 0, "direction": mc.MAP_FLAG_DIRECTION}
+    mode_names = list(modes) if args.serve_mode == "tune" else [args.serve_mode]
+    tsample = queries()[:min(count, 200)]
+    tuner, best = {}, None
+    for mname in mode_names:
+        with serve.Server(hbm_budget=budget, flags=modes[mname]) as srv:
+            serve.run_stream(queries()[:16], qps=1e9, server=srv)  # warm-up
 
             def trial(pol):
                 srv.gang_policy = (lambda ns, ms: autotune.gang_sizes(ns, ms, pol)) if pol else None
                 return serve.run_stream([serve.Query(q.qid, q.n, q.src, q.dst, q.acc) for q in tsample],
                                         qps=1e9, server=srv)["span_s"]
-            policy, tuner = autotune.tune_by(trial, log=lambda x: print(x, file=sys.stderr, flush=True))
-        else:
-            policy, tuner = autotune.parse_policy(args.serve_policy), None
+            if args.serve_policy == "tune":
+                pol, t = autotune.tune_by(trial, log=lambda x: print(f"[{mname}] {x}", file=sys.stderr, flush=True))
+                tuner.update({f"{mname}|{k}": v for k, v in t.items()})
+                span = t[autotune.policy_name(pol)]
+            else:
+                pol = autotune.parse_policy(args.serve_policy)
+                span = trial(pol) if len(mode_names) > 1 else 0.0
+                tuner[f"{mname}|{args.serve_policy}"] = span
+        if best is None or span < best[0]:
+            best = (span, mname, pol)
+    _, mode, policy = best
+    with serve.Server(hbm_budget=budget, flags=modes[mode]) as srv:
+        warm = queries()[:16]
+        serve.run_stream(warm, qps=1e9, server=srv)             # warm-up
         srv.gang_policy = (lambda ns, ms: autotune.gang_sizes(ns, ms, policy)) if policy else None
         srv.max_running = 0
         qs = queries()
@@ -400,7 +415,7 @@ def bench_serve(args):
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": WORKLOADS["c5"][0], "key": "c5", "queries": count, "rho": args.rho,
                    "offered_qps": round(qps, 3), "hbm_budget_gib": budget >> 30, "engine_workgroups": workgroups,
-                   "gang_policy": autotune.policy_name(policy), "parallelism": "single GPU"},
+                   "gang_policy": autotune.policy_name(policy), "engine_mode": mode, "parallelism": "single GPU"},
         "serving": rnd(st),
         "serial_plain": rnd(ser),
         "serial_saturated_graphs_per_s": round(rate, 3),
@@ -761,6 +776,8 @@ def main():
     ap.add_argument("--rho-over", type=float, default=1.5, help="second, overloaded stream (0: skip)")
     ap.add_argument("--serve-policy", default="tune",
                     help="gang policy when serving: tune, one, or EDGES[+fit] (edges per workgroup)")
+    ap.add_argument("--serve-mode", default="tune", choices=["tune", "pull", "direction"],
+                    help="engine sweeps when serving: pull (as map_detect) or filtered with the direction switch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the detector runs on one GPU; --gpus {args.gpus} is not supported "

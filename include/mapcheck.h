@@ -380,7 +380,10 @@ typedef struct map_job {
   uint64_t tag;               /* free for the caller; not read by the engine */
 } map_job;
 
-/* Bytes of device scratch one job needs (0 when n or m is out of range). */
+/* Bytes of device scratch one job needs (0 when n or m is out of range): the
+ * packed values and working flags (5n), the filtered sweeps' four bitmaps
+ * (n / 2), scan partials, a staged copy of a host edge list (8m) and the
+ * transposed CSR (4n + 4m) that MAP_FLAG_DIRECTION builds. */
 size_t map_job_scratch_bytes(int32_t n, int64_t m);
 
 /*
@@ -389,7 +392,11 @@ size_t map_job_scratch_bytes(int32_t n, int64_t m);
  *   workgroups    0 = all but one compute unit in 32; else at most that many.
  *   idle_seconds  the kernel exits by itself after this long without a job
  *                 (every later submit returns MAP_EDEVICE); (0, 86400].
- *   flags         MAP_FLAG_STREAM / MAP_FLAG_SYNC_SWEEPS as for map_detect.
+ *   flags         MAP_FLAG_STREAM / MAP_FLAG_SYNC_SWEEPS as for map_detect;
+ *                 MAP_FLAG_DIRECTION: each job also builds the transposed CSR
+ *                 of its graph in its scratch and runs filtered stream sweeps
+ *                 with the direction switch (MAP_GRAPH_FILTER |
+ *                 MAP_GRAPH_DIRECTION of a batch); no result changes.
  *   stream        the engine kernel's stream; keep other work off it.
  *   out           the engine handle.
  * Returns MAP_EDEVICE when allocation or the launch fails.

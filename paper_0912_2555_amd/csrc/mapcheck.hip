@@ -2632,21 +2632,21 @@ __device__ __forceinline__ void for_edges(const int32_t* src, const int32_t* dst
 // gang barrier timed out; *bad = edges with an endpoint outside 1..n (the CSR
 // is then unspecified and the gang stops after the histogram).
 __device__ bool gang_build_csr(const map_job& j, int32_t* cursor, uint32_t* part, int32_t* stage_src,
-                               int32_t* stage_dst, Grid<GangCtrl>& g, int nb, int rank, uint32_t* bad) {
+                               int32_t* stage_dst, Grid<GangCtrl>& g, int nb, int rank, uint32_t* bad,
+                               int32_t* rp, int32_t* col, const int32_t* esrc, const int32_t* edst, bool swap) {
   const int32_t n = j.n;
   const int64_t m = j.m;
-  int32_t* rp = j.row_ptr;
   const int64_t gt = (int64_t)rank * kBlock + threadIdx.x, gs = (int64_t)nb * kBlock;
   for (int64_t i = gt; i <= n; i += gs) rp[i] = 0;
   if (!grid_sync(g, 0u, nullptr)) return false;
   // Degree histogram: the count of row v (vertex v+1) lands at rp[v+1].
   uint32_t nbad = 0;
-  for_edges(j.src, j.dst, m, gt, gs, stage_src, stage_dst, [&](int32_t s, int32_t d) {
+  for_edges(esrc, edst, m, gt, gs, stage_src, stage_dst, [&](int32_t s, int32_t d) {
     if (s < 1 || s > n || d < 1 || d > n) {
       ++nbad;
       return;
     }
-    __hip_atomic_fetch_add(&rp[s], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&rp[swap ? d : s], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   });
   nbad = block_sum_u32(nbad);
   uint32_t tot = 0;
@@ -2675,12 +2675,12 @@ __device__ bool gang_build_csr(const map_job& j, int32_t* cursor, uint32_t* part
   if (!grid_sync(g, 0u, nullptr)) return false;
   for (int64_t r = gt; r < n; r += gs) cursor[r] = rp[r];
   if (!grid_sync(g, 0u, nullptr)) return false;
-  int32_t* col = j.col;
-  const int32_t* src = stage_src ? stage_src : j.src;
-  const int32_t* dst = stage_src ? stage_dst : j.dst;
+  const int32_t* src = stage_src ? stage_src : esrc;
+  const int32_t* dst = stage_src ? stage_dst : edst;
   for_edges(src, dst, m, gt, gs, nullptr, nullptr, [&](int32_t s, int32_t d) {
-    const int32_t pos = __hip_atomic_fetch_add(&cursor[s - 1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    col[pos] = d - 1;
+    const int32_t r = swap ? d : s, c = swap ? s : d;
+    const int32_t pos = __hip_atomic_fetch_add(&cursor[r - 1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    col[pos] = c - 1;
   });
   return grid_sync(g, 0u, nullptr);
 }
@@ -2704,8 +2704,17 @@ __device__ __noinline__ void engine_job(const EngineArgs& ea, int slot, int rank
   GangCtrl* mcx = ea.mctrl + slot;
   map_result* res = ea.dres + slot;
   char* sc = static_cast<char*>(j.scratch);
+  // Scratch: packed values | working flags | bitmaps of the filtered sweeps |
+  // scan partials | staged edge list (src, dst) | transposed CSR.
   const size_t pv_bytes = ((size_t)j.n * 4 + 255) & ~(size_t)255;
   const size_t acc_bytes = ((size_t)j.n + 255) & ~(size_t)255;
+  const size_t bm_bytes = 4 * (size_t)gang_bitmap_bytes(j.n);
+  const size_t edge_bytes = ((size_t)j.m * 4 + 255) & ~(size_t)255;
+  char* part = sc + pv_bytes + acc_bytes + bm_bytes;
+  char* stage = part + (size_t)kMaxGang * 4;
+  int32_t* rrow = reinterpret_cast<int32_t*>(stage + 2 * edge_bytes);
+  int32_t* rcol = reinterpret_cast<int32_t*>(stage + 2 * edge_bytes + (((size_t)j.n * 4 + 4 + 255) & ~(size_t)255));
+  const bool dir = (ea.flags & MAP_FLAG_DIRECTION) != 0;
 
   if (rank == 0) {
     uint32_t* pb = reinterpret_cast<uint32_t*>(bc);
@@ -2740,14 +2749,19 @@ __device__ __noinline__ void engine_job(const EngineArgs& ea, int slot, int rank
   uint32_t bad = 0;
   if (ok) {
     Grid<GangCtrl> g = make_grid(bc, nb, rank);
-    char* stage = sc + pv_bytes + acc_bytes + (size_t)kMaxGang * 4;
-    const size_t edge_bytes = ((size_t)j.m * 4 + 255) & ~(size_t)255;
-    ok = gang_build_csr(j, reinterpret_cast<int32_t*>(sc), reinterpret_cast<uint32_t*>(sc + pv_bytes + acc_bytes),
-                        ej.host_edges ? reinterpret_cast<int32_t*>(stage) : nullptr,
-                        ej.host_edges ? reinterpret_cast<int32_t*>(stage + edge_bytes) : nullptr, g, nb, rank, &bad);
+    int32_t* ss = ej.host_edges ? reinterpret_cast<int32_t*>(stage) : nullptr;
+    int32_t* sd = ej.host_edges ? reinterpret_cast<int32_t*>(stage + edge_bytes) : nullptr;
+    ok = gang_build_csr(j, reinterpret_cast<int32_t*>(sc), reinterpret_cast<uint32_t*>(part), ss, sd, g, nb, rank,
+                        &bad, j.row_ptr, j.col, j.src, j.dst, false);
+    // MAP_FLAG_DIRECTION: the transposed CSR too, from the staged copy of a
+    // host edge list.
+    if (ok && bad == 0 && dir)
+      ok = gang_build_csr(j, reinterpret_cast<int32_t*>(sc), reinterpret_cast<uint32_t*>(part), nullptr, nullptr, g,
+                          nb, rank, &bad, rrow, rcol, ss ? ss : j.src, ss ? sd : j.dst, true);
   }
   if (ok && bad == 0) {
-    const LoopArgs a = gang_args(j.n, j.row_ptr, j.col, nullptr, nullptr, j.accepting0, sc, res, ea.flags, 0);
+    const LoopArgs a = gang_args(j.n, j.row_ptr, j.col, dir ? rrow : nullptr, dir ? rcol : nullptr, j.accepting0, sc,
+                                 res, ea.flags, dir ? (MAP_GRAPH_FILTER | MAP_GRAPH_DIRECTION) : 0);
     map_body_gang(a, mcx, nb, rank);
   }
   // Leave the job: release this block's writes, then report (ranks > 0) or
@@ -4145,8 +4159,11 @@ int map_detect_batch(int32_t count, const map_graph_desc* graphs, const int32_t*
 
 size_t map_job_scratch_bytes(int32_t n, int64_t m) {
   if (!sizes_ok(n, m)) return 0;
-  // packed values | working flags | scan partials | staged edge list (src, dst)
-  return align256((size_t)n * 4) + align256((size_t)n) + (size_t)kMaxGang * 4 + 2 * align256((size_t)m * 4);
+  // packed values | working flags | bitmaps of the filtered sweeps | scan
+  // partials | staged edge list (src, dst) | transposed CSR (the last three
+  // parts used with MAP_FLAG_DIRECTION only)
+  return align256((size_t)n * 4) + align256((size_t)n) + 4 * (size_t)gang_bitmap_bytes(n) + (size_t)kMaxGang * 4 +
+         2 * align256((size_t)m * 4) + align256((size_t)n * 4 + 4) + align256((size_t)m * 4);
 }
 
 static void engine_free(map_engine* e) {

@@ -130,14 +130,17 @@ class Server:
     """Continuous-batching MAP server on one running map_engine."""
 
     def __init__(self, hbm_budget: int = 32 << 30, gang_policy=None, max_jobs: int = 1024, workgroups: int = 0,
-                 idle_seconds: float = 60.0, device="cuda"):
+                 idle_seconds: float = 60.0, device="cuda", flags: int = 0):
         self.device = torch.device(device)
         self.budget = hbm_budget
         self.gang_policy = gang_policy      # callable(list of n, list of m) -> gang sizes, or None (1 each)
         self.arena_mem = torch.empty(hbm_budget, dtype=torch.uint8, device=self.device)
         self.arena = Arena(hbm_budget)
         torch.cuda.synchronize(self.device)
-        self.engine = mc.Engine(max_jobs=max_jobs, workgroups=workgroups, idle_seconds=idle_seconds,
+        # flags: MAP_FLAG_DIRECTION runs every query with filtered sweeps and the
+        # direction switch (its scratch already has room for the transposed CSR)
+        self.flags = flags
+        self.engine = mc.Engine(max_jobs=max_jobs, workgroups=workgroups, idle_seconds=idle_seconds, flags=flags,
                                 device=self.device)
         self.waiting: collections.deque = collections.deque()   # arrived, not admitted
         self.admitted: collections.deque = collections.deque()  # admitted, not yet taken by the engine

@@ -173,7 +173,8 @@ def test_engine_host_side_errors_without_device(lib):
     lib.map_engine_destroy.argtypes = [vp]
     lib.map_engine_workgroups.argtypes = [vp]
     # scratch: packed values (4n) + flags (n), each 256-aligned, + per-rank scan partials + staged edges (2 x 4m)
-    assert lib.map_job_scratch_bytes(1000, 5000) == 4096 + 1024 + 1024 + 2 * 20224
+    # values | flags | four bitmaps | scan partials | staged edges | transposed CSR
+    assert lib.map_job_scratch_bytes(1000, 5000) == 4096 + 1024 + 4 * 256 + 1024 + 2 * 20224 + 4096 + 20224
     assert lib.map_job_scratch_bytes(0, 5) == 0
     assert lib.map_job_scratch_bytes(10, -1) == 0
     h = vp()

@@ -99,6 +99,19 @@ def test_engine_jobs_match_oracle_and_csr(mc):
     _check(mc, jobs)
 
 
+def test_engine_direction_jobs_match_oracle_and_csr(mc):
+    """MAP_FLAG_DIRECTION: each job also builds its transposed CSR and runs
+    filtered sweeps with push rounds on small frontiers; results exact."""
+    gs = _graphs()
+    gangs = [1, 2, 3, 8, 1, 4]
+    jobs = [_Job(mc, g, gangs[i % len(gangs)], host=i % 2 == 0) for i, g in enumerate(gs)]
+    import torch
+    torch.cuda.synchronize()
+    with mc.Engine(max_jobs=64, idle_seconds=30.0, flags=mc.MAP_FLAG_DIRECTION) as eng:
+        _run(mc, eng, jobs)
+    _check(mc, jobs)
+
+
 def test_engine_slot_reuse_when_full(mc):
     gs = [synth.random_graph(900 + i, 200 + 37 * i, 600 + 50 * i, p_acc=0.2) for i in range(16)]
     jobs = [_Job(mc, g, 1 + i % 3) for i, g in enumerate(gs)]

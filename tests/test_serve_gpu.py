@@ -35,7 +35,7 @@ def test_serving_mix_equals_alone(mods):
         csr = mc.build_csr(g.n, g.src, g.dst, transposed=False)
         alone.append(mc.detect(csr, g.acc).result)
     qs = [serve.Query(i, g.n, g.src, g.dst, g.acc) for i, g in enumerate(gs)]
-    budget = 24 << 20                                            # small: admission must queue
+    budget = 40 << 20                                            # small: admission must queue
     assert sum(serve.footprint(g.n, g.m) for g in gs) > budget
     with serve.Server(hbm_budget=budget, idle_seconds=30.0) as srv:
         stats = serve.run_stream(qs, qps=2000.0, server=srv)
