@@ -42,13 +42,17 @@ def _exact(res, refs):
                for r, f in zip(res, refs))
 
 
-@pytest.mark.parametrize("policy", ["one-per-graph", "gangs"])
+@pytest.mark.parametrize("policy", ["one-per-graph", "gangs", "one-per-graph-direction", "gangs-direction"])
 def test_captured_batch_replays_exact(mc, batch, policy):
     import torch
     gs, refs = batch
-    csrs = [mc.build_csr(g.n, g.src, g.dst, transposed=False) for g in gs]
-    gang = None if policy == "one-per-graph" else [1 if g.n < 20_000 else 4 for g in gs]
-    options = [mc.MAP_GRAPH_SYNC_SWEEPS if i % 3 == 0 else 0 for i in range(len(gs))]
+    direction = policy.endswith("-direction")
+    csrs = [mc.build_csr(g.n, g.src, g.dst, transposed=direction) for g in gs]
+    gang = None if policy.startswith("one-per-graph") else [1 if g.n < 20_000 else 4 for g in gs]
+    if direction:   # filtered sweeps with the direction switch on most graphs, plain ones between
+        options = [0 if i % 4 == 3 else mc.MAP_GRAPH_FILTER | mc.MAP_GRAPH_DIRECTION for i in range(len(gs))]
+    else:
+        options = [mc.MAP_GRAPH_SYNC_SWEEPS if i % 3 == 0 else 0 for i in range(len(gs))]
     b = mc.Batch(csrs, [g.acc for g in gs], gang=gang, options=options)
     say("capture", policy, "graphs", len(gs))
     s = torch.cuda.Stream()
