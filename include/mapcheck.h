@@ -323,7 +323,9 @@ typedef struct map_graph_desc {
 
 /*
  * Bytes of device workspace for map_detect_batch over `count` graphs whose
- * vertex counts sum to total_n (host only; 0 when out of range).
+ * vertex counts sum to total_n (host only; 0 when out of range).  It holds
+ * every graph's scratch with the room MAP_GRAPH_FILTER needs, whatever the
+ * options.
  */
 size_t map_batch_workspace_bytes(int32_t count, int64_t total_n, uint32_t flags);
 
