@@ -299,7 +299,7 @@ typedef struct map_graph_desc {
   const int32_t *row_ptr;     /* device pull CSR from map_build_csr: int32[n+1] */
   const int32_t *col;         /* device int32[m] */
   const uint8_t *accepting0;  /* device uint8[n]: A_1, not modified */
-  const int32_t *rrow_ptr;    /* device transposed CSR (successors) from map_build_csr, or NULL: int32[n+1] */
+  const int32_t *rrow_ptr;    /* device transposed CSR (row v: predecessors of v) from map_build_csr, or NULL: int32[n+1] */
   const int32_t *rcol;        /* device int32[m], or NULL; read only with MAP_GRAPH_DIRECTION */
 } map_graph_desc;
 
