@@ -162,6 +162,22 @@ def test_strerror(lib):
     assert lib.map_strerror(99).decode() == "unknown status"
 
 
+def test_batch_workspace_covers_filtered_scratch(lib):
+    """The batch workspace grows with the graphs at least as fast as their
+    scratch with MAP_GRAPH_FILTER does: values (4n) and flags (n), each
+    256-aligned, and four 256-aligned bitmaps of ceil(n / 32) words."""
+    lib.map_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32]
+    lib.map_batch_workspace_bytes.restype = ctypes.c_size_t
+    al = lambda x: (x + 255) // 256 * 256
+    per = lambda n: al(4 * n) + al(n) + 4 * al((n + 31) // 32 * 4)
+    for ns in ([1000], [1, 2, 3], [10**6, 999_999, 31, 33], [257] * 100, [1 << 20] * 3):
+        c = len(ns)
+        grown = lib.map_batch_workspace_bytes(c, sum(ns), 0) - lib.map_batch_workspace_bytes(c, c, 0)
+        assert grown >= sum(per(n) for n in ns) - c * per(1), ns
+    # the least workspace (every graph n = 1) holds c scratches of n = 1
+    assert lib.map_batch_workspace_bytes(7, 7, 0) >= 7 * per(1)
+
+
 def test_engine_host_side_errors_without_device(lib):
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.map_job_scratch_bytes.argtypes = [i32, i64]
@@ -172,8 +188,7 @@ def test_engine_host_side_errors_without_device(lib):
     lib.map_engine_stop.argtypes = [vp]
     lib.map_engine_destroy.argtypes = [vp]
     lib.map_engine_workgroups.argtypes = [vp]
-    # scratch: packed values (4n) + flags (n), each 256-aligned, + per-rank scan partials + staged edges (2 x 4m)
-    # values | flags | four bitmaps | scan partials | staged edges | transposed CSR
+    # values | flags | four bitmaps | scan partials | staged edges | transposed CSR, each 256-aligned
     assert lib.map_job_scratch_bytes(1000, 5000) == 4096 + 1024 + 4 * 256 + 1024 + 2 * 20224 + 4096 + 20224
     assert lib.map_job_scratch_bytes(0, 5) == 0
     assert lib.map_job_scratch_bytes(10, -1) == 0
