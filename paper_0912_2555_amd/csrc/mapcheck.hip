@@ -3425,7 +3425,7 @@ __global__ void __launch_bounds__(kRadixThreads)
   }
   __syncthreads();
   if (wib == 0) {
-    // Exclusive scan of the digit totals, 8 digits per lane.
+    // Exclusive scan of the digit totals, kRadixBins / 64 digits per lane.
     uint32_t v[kRadixBins / kWave], sum = 0;
 #pragma unroll
     for (int j = 0; j < kRadixBins / kWave; ++j) {
