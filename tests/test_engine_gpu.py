@@ -110,6 +110,23 @@ def test_engine_direction_jobs_match_oracle_and_csr(mc):
     with mc.Engine(max_jobs=64, idle_seconds=30.0, flags=mc.MAP_FLAG_DIRECTION) as eng:
         _run(mc, eng, jobs)
     _check(mc, jobs)
+    # The transposed CSR each job built in its scratch (after the packed values,
+    # flags, four bitmaps, scan partials and the staged edge list, each part
+    # 256-aligned) equals map_build_csr's, row by row as a multiset.
+    al = lambda x: (x + 255) // 256 * 256
+    for j in jobs:
+        n, m = j.g.n, j.g.m
+        if m == 0:
+            continue
+        ref = mc.build_csr(n, j.g.src, j.g.dst, transposed=True)
+        off = al(4 * n) + al(n) + 4 * al((n + 31) // 32 * 4) + 256 * 4 + 2 * al(4 * m)
+        sc = j.scratch.cpu().numpy()
+        rp = sc[off:off + 4 * (n + 1)].view(np.int32)
+        col = sc[off + al(4 * n + 4):off + al(4 * n + 4) + 4 * m].view(np.int32)
+        assert np.array_equal(rp, ref.rrow_ptr.cpu().numpy()), j.g.name
+        rcol = ref.rcol.cpu().numpy()
+        rows = np.repeat(np.arange(n), np.diff(rp))
+        assert np.array_equal(col[np.lexsort((col, rows))], rcol[np.lexsort((rcol, rows))]), j.g.name
 
 
 def test_engine_slot_reuse_when_full(mc):
