@@ -215,9 +215,11 @@ def tune_knobs(make_batch, ns, ms, dmaxs, device_name: str, reps: int = 2, use_c
             best_rule, best_t = rule, t
     if best_rule != "default":
         # The gang policies again, under the chosen option rule (an option such
-        # as the direction switch changes which gang size pays).
+        # as the direction switch changes which gang size pays); the first
+        # stage's winner was timed under the rule already.
+        first = best_gang
         for cand in gang_candidates:
-            if cand == best_gang:
+            if cand == first:
                 continue
             g2 = gang_sizes(ns, ms, cand)
             t = time_batch(g2, graph_options(best_rule, g2, ns, dmaxs))

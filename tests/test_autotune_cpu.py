@@ -43,3 +43,41 @@ def test_option_bits_match_the_header():
     assert int(vals["MAP_GRAPH_HUB_MASK"], 16) == autotune.HUB_NEVER
     assert int(vals["MAP_GRAPH_FILTER"], 16) == autotune.GRAPH_FILTER
     assert int(vals["MAP_GRAPH_DIRECTION"], 16) == autotune.GRAPH_DIRECTION
+
+
+def test_tune_knobs_retunes_the_gang_under_the_winning_rule(monkeypatch, tmp_path):
+    """With a launch whose time depends on both knobs, the tuner takes the
+    fastest gang policy at default options, the fastest rule on it, then the
+    fastest gang policy under that rule -- here a different one -- and caches
+    the pair."""
+    import time
+    import torch
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
+    monkeypatch.setenv("MAPCHECK_TUNE_CACHE", str(tmp_path / "tune.json"))
+    ns, ms, dmax = [1000, 2000], [4000, 8000], [3, 4]
+    one, wide = None, (1 << 14, False)
+    fd = autotune.GRAPH_FILTER | autotune.GRAPH_DIRECTION
+    # seconds per launch: default options favour `wide`; the direction rule is
+    # faster still, and under it one workgroup per graph wins
+    cost = {(autotune.policy_name(one), 0): 0.004, (autotune.policy_name(wide), 0): 0.002,
+            (autotune.policy_name(one), fd): 0.0005, (autotune.policy_name(wide), fd): 0.001}
+
+    class FakeBatch:
+        def __init__(self, gangs, options):
+            pol = one if gangs is None else wide
+            opt = 0 if options is None else options[0]
+            self.t = cost.get((autotune.policy_name(pol), opt), 0.003)
+
+        def launch(self):
+            time.sleep(self.t)
+
+    choice, timings = autotune.tune_knobs(FakeBatch, ns, ms, dmax, "fake", reps=1, use_cache=True,
+                                          gang_candidates=(one, wide),
+                                          rules=("default", "filter-all", "direction-all"))
+    assert choice == {"gang": one, "options": "direction-all"}, (choice, timings)
+    assert "gang:one|direction-all" in timings
+    assert "gang:16384|direction-all" not in timings        # the first stage's winner is not timed twice
+    assert timings["gang:" + autotune.policy_name(wide)] < timings["gang:one"]
+    again, _ = autotune.tune_knobs(FakeBatch, ns, ms, dmax, "fake", reps=1, use_cache=True,
+                                   gang_candidates=(one, wide))
+    assert again == choice                                  # from the cache
