@@ -7,7 +7,7 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-LIB = os.path.join(ROOT, "paper_0912_2555_amd", "libmapcheck.so")
+LIB = os.environ.get("MAPCHECK_LIB") or os.path.join(ROOT, "paper_0912_2555_amd", "libmapcheck.so")
 HEADER = os.path.join(ROOT, "include", "mapcheck.h")
 
 MAP_OK, MAP_EINVAL, MAP_ERANGE, MAP_ENOSPC = 0, -1, -2, -3
